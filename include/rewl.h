@@ -1,0 +1,199 @@
+/*
+ * librewl -- replica-exchange Wang-Landau (REWL) sampling on one MI355X.
+ *
+ * Method: Li, Vogel, Wuest, Landau, "A new paradigm for petascale Monte Carlo
+ * simulation: Replica exchange Wang-Landau sampling" (arXiv:1402.2328).
+ *   Sec. 2  standard Wang-Landau: a trial move is accepted with
+ *           min[1, g(E_old)/g(E_new)]; after every attempt g(E) -> f g(E) and
+ *           H(E) += 1 at the current energy; when H is flat, H is reset and
+ *           f -> sqrt(f); the run ends at f_final.
+ *   Sec. 2  REWL: the energy range is split into h overlapping windows
+ *           (Fig. 1a, overlap o); m walkers per window, each with its own g
+ *           and H; every so many MC steps a walker swaps configurations with a
+ *           random walker of a neighbouring window with probability Eq. (1),
+ *           min[1, g_i(E(X))/g_i(E(Y)) * g_j(E(Y))/g_j(E(X))]; a pair with an
+ *           energy outside the other's window is disregarded; when all m
+ *           walkers of a window are flat their g are averaged and
+ *           redistributed; each window has its own f; the run ends when every
+ *           window reached f_final.
+ *   Sec. 3  the h pieces are joined where the slopes d ln g/dE agree best
+ *           (Eq. 2), using a 5-point derivative (Fig. 2).
+ *   Sec. 5  Eqs. (5)-(6): <E> and C_V from g(E).
+ *
+ * Models: 2D Ising (E = -sum s_i s_j, s = +-1) and q-state Potts
+ * (E = -sum delta(s_i, s_j)) on a periodic L x L lattice, single-site moves.
+ * Energies are binned: bin b = (E - E_min)/binw with E_min = -2N, binw 4
+ * (Ising), 2 (Potts q = 2) or 1 (Potts q >= 3).
+ *
+ * Conventions
+ *   - Every function returns 0 (REWL_OK) or a negative REWL_E_* code and never
+ *     throws.  rewl_strerror() names a code.
+ *   - Device memory: the caller allocates one device buffer of
+ *     rewl_workspace_bytes() bytes (any allocator, e.g. a torch tensor) and
+ *     keeps it alive until rewl_destroy().  The library writes all simulation
+ *     state into it and allocates no device memory of its own.  The library
+ *     owns only the host-side context object.
+ *   - Streams: run/merge/exchange/init calls only enqueue work on the
+ *     hipStream_t given to rewl_init (a null pointer means the legacy default
+ *     stream) and return without synchronising.  rewl_status, rewl_get_*,
+ *     rewl_thermo, rewl_checkpoint and rewl_restore synchronise that stream.
+ *   - Calls on one context are not thread-safe.  Per cycle the call order is
+ *     rewl_run_sweeps -> rewl_merge -> rewl_exchange.
+ *   - A batch of n_instances independent REWL instances shares one context;
+ *     instance i draws its random numbers from counters that carry i, so an
+ *     instance gives bit-identical results alone or inside any batch.
+ */
+#ifndef REWL_H
+#define REWL_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  REWL_OK = 0,
+  REWL_E_INVAL = -1,     /* invalid argument or parameter set */
+  REWL_E_NOMEM = -2,     /* workspace too small / host allocation failed */
+  REWL_E_HIP = -3,       /* a HIP runtime call failed */
+  REWL_E_NONFINITE = -4, /* a non-finite ln g value was found */
+  REWL_E_OVERFLOW = -5,  /* a histogram counter reached 2^31 */
+  REWL_E_STATE = -6,     /* call not valid in the current state */
+  REWL_E_WARMUP = -7,    /* a walker could not be brought into its window */
+  REWL_E_FORMAT = -8     /* checkpoint blob does not match this context */
+};
+
+enum { REWL_ISING = 0, REWL_POTTS = 1 };
+enum { REWL_FP64 = 0, REWL_FP32C = 1 };
+
+/* One REWL instance.  All instances of one context must share `precision`. */
+typedef struct {
+  int32_t model;              /* REWL_ISING or REWL_POTTS */
+  int32_t L;                  /* periodic L x L lattice, 2 <= L <= 64 */
+  int32_t q;                  /* Potts states, 2..127 (ignored for Ising) */
+  int32_t n_windows;          /* h >= 1 */
+  int32_t overlap_num;        /* overlap o = num/den of the equal-size split */
+  int32_t overlap_den;
+  int32_t walkers_per_window; /* m >= 1 */
+  int32_t flat_num;           /* flatness: min H >= (num/den) mean H */
+  int32_t flat_den;
+  int32_t precision;          /* REWL_FP64, or REWL_FP32C: two-float ln g */
+  double lnf_init;            /* ln f_0 > 0 */
+  double lnf_final;           /* window frozen once ln f <= lnf_final */
+  int64_t flips_per_exchange; /* F: attempts per walker per cycle (informative) */
+  uint64_t seed;              /* Philox4x32-10 key */
+} rewl_params;
+
+typedef struct rewl_ctx rewl_ctx;
+
+/* Device bytes needed for `n` instances.  win_lo/win_hi: NULL for the
+ * equal-size split of every instance, or arrays concatenating, instance by
+ * instance, n_windows inclusive global-bin edges (explicit windows, e.g. a
+ * run-time balanced split, Fig. 1b).  Returns 0 for invalid input. */
+size_t rewl_workspace_bytes(const rewl_params* params, int32_t n_instances,
+                            const int32_t* win_lo, const int32_t* win_hi);
+
+/* Builds the context, lays out the workspace and enqueues initialisation:
+ * random spins, full energies, warm-up of every walker into its window
+ * (greedy moves, restart from an extreme state), ln g = 0, H = 0,
+ * ln f = lnf_init.  params: n_instances entries.  d_workspace: device
+ * pointer to >= rewl_workspace_bytes() bytes.  stream: hipStream_t or NULL.
+ * Errors: INVAL (bad parameters), NOMEM (workspace too small), HIP. */
+int rewl_init(const rewl_params* params, int32_t n_instances,
+              const int32_t* win_lo, const int32_t* win_hi,
+              void* d_workspace, size_t workspace_bytes, void* stream, rewl_ctx** out);
+
+/* Enqueues `flips` Wang-Landau attempts for every walker of every instance
+ * that is not finished (Sec. 2).  Frozen windows keep moving without updating
+ * ln g or H.  Errors: INVAL (flips < 0), HIP. */
+int rewl_run_sweeps(rewl_ctx* ctx, int64_t flips);
+
+/* Enqueues the flatness test and in-window merge for every non-frozen window
+ * (Sec. 2): when all m walkers of a window are flat at this check, their ln g
+ * are averaged (pairwise sum in walker order, divided by m), H is reset and
+ * ln f halves; the window freezes once ln f <= lnf_final.  An instance whose
+ * windows are all frozen is finished.  Errors: HIP. */
+int rewl_merge(rewl_ctx* ctx);
+
+/* Enqueues one replica-exchange round (Eq. 1) for every unfinished instance:
+ * round t pairs windows (w, w+1) with w = t mod 2; walker k of window w is
+ * paired with walker pi(k) of window w+1, pi uniform; configurations are
+ * swapped by exchanging configuration indices.  Errors: HIP. */
+int rewl_exchange(rewl_ctx* ctx);
+
+/* Enqueues `cycles` x (run_sweeps(flips) -> merge -> exchange).  With
+ * use_graph != 0 the sequence is captured once into a hipGraph and replayed.
+ * Errors: INVAL, HIP. */
+int rewl_run_cycles(rewl_ctx* ctx, int64_t cycles, int64_t flips, int32_t use_graph);
+
+typedef struct {
+  int32_t done;          /* every window frozen */
+  int32_t error;         /* 0 or a REWL_E_* code raised on the device */
+  int64_t done_merge;    /* merge index at which the last window froze, -1 */
+  int64_t merges;        /* merge calls executed while unfinished */
+  uint64_t rounds;       /* exchange rounds executed */
+  uint64_t attempts;     /* MC attempts summed over the instance's walkers */
+} rewl_instance_status;
+
+/* Synchronises.  out: one entry.  stage_per_window / frozen_per_window /
+ * lnf_per_window: NULL or n_windows entries. */
+int rewl_status(rewl_ctx* ctx, int32_t instance, rewl_instance_status* out,
+                int32_t* stage_per_window, int32_t* frozen_per_window, double* lnf_per_window);
+
+/* Synchronises.  Number of instances neither finished nor failed. */
+int rewl_running(rewl_ctx* ctx, int32_t* n_running);
+
+/* Synchronises.  which = 0: ln g joined over all windows (Sec. 3, Eq. 2) in
+ * FP64 and normalised (Ising: sum g = 2^N; Potts: g(E_min) = q); which = 1:
+ * joined, not normalised.  host_out: capacity doubles, receives nbins values
+ * (-inf where no walker of the supplying window visited); joins: NULL or
+ * n_windows-1 join bins.  Errors: INVAL (capacity too small), HIP. */
+int rewl_get_lng(rewl_ctx* ctx, int32_t instance, int32_t which, double* host_out,
+                 int32_t capacity, int32_t* n_bins_out, int32_t* joins);
+
+/* Synchronises.  Geometry of an instance: N, nbins, binw, E_min, h, m, first
+ * global walker slot, and the window edges (NULL allowed). */
+int rewl_get_geometry(rewl_ctx* ctx, int32_t instance, int32_t* N, int32_t* nbins,
+                      int32_t* binw, int32_t* emin, int32_t* h, int32_t* m,
+                      int32_t* first_slot, int32_t* win_lo, int32_t* win_hi);
+
+/* Synchronises.  State of one walker (instance-local slot = w*m + k): the
+ * spins of the configuration it carries (N int8), its energy, H and ln g over
+ * its window (FP64; FP32C gives hi + lo widened), its attempt counter and
+ * the identity (index) of the configuration.  Any pointer may be NULL. */
+int rewl_get_walker(rewl_ctx* ctx, int32_t instance, int32_t slot, int8_t* spins,
+                    int32_t* energy, uint32_t* H, double* lng, uint64_t* attempts,
+                    int32_t* config_id);
+/* FP32C only: the two-float parts of a walker's ln g. */
+int rewl_get_walker_f32(rewl_ctx* ctx, int32_t instance, int32_t slot, float* hi, float* lo);
+/* Synchronises.  Visited-union mask of a window (nb_w bytes). */
+int rewl_get_visited(rewl_ctx* ctx, int32_t instance, int32_t window, uint8_t* mask);
+/* Synchronises.  Per lower window w of pair (w, w+1): proposals, proposals
+ * with both energies inside the partner window, accepted swaps (h entries). */
+int rewl_get_exchange_stats(rewl_ctx* ctx, int32_t instance, uint64_t* tries,
+                            uint64_t* in_range, uint64_t* accepts);
+
+/* Synchronises.  Canonical <E> and C_V (Eqs. 5-6, k_B = 1) from the joined,
+ * normalised ln g of an instance, evaluated on the GPU in FP64 for nT
+ * temperatures.  Errors: INVAL, HIP. */
+int rewl_thermo(rewl_ctx* ctx, int32_t instance, const double* T, int32_t nT,
+                double* E_mean, double* C_v);
+
+/* Synchronises.  Serialises the whole simulation state into host_buf
+ * (capacity cap bytes); *used receives the size (call with host_buf = NULL
+ * to query).  rewl_restore loads such a blob into a context built with the
+ * same parameters; a restored run continues bit-identically.  Errors: NOMEM
+ * (cap too small), FORMAT (blob from another configuration), HIP. */
+int rewl_checkpoint(rewl_ctx* ctx, void* host_buf, size_t cap, size_t* used);
+int rewl_restore(rewl_ctx* ctx, const void* host_buf, size_t n);
+
+/* Frees the host context (the caller frees the workspace). */
+int rewl_destroy(rewl_ctx* ctx);
+
+const char* rewl_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,657 @@
+// Host side of librewl: the C-ABI declared in include/rewl.h.
+//
+// The host validates parameters, derives bins and windows, lays the whole
+// simulation state out in the caller's device workspace, builds the
+// walker-to-workgroup table for the sweep kernel and enqueues kernels on the
+// caller's stream.  It never allocates device memory.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "../../include/rewl.h"
+#include "rewl_internal.h"
+
+using namespace rewl;
+
+namespace {
+
+constexpr uint64_t kCkptMagic = 0x3130304c5745524bULL;  // "KREWL001"
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Layout {
+  std::vector<InstDesc> inst;
+  std::vector<WinDesc> win;
+  std::vector<WgDesc> wg;
+  int32_t n_wg_ising = 0;
+  int32_t n_slots = 0;
+  int64_t spin_bytes = 0;
+  int64_t lng_elems = 0;
+  int32_t u_elems = 0;
+  int32_t rep_elems = 0;
+  int32_t r_elems = 0;
+  int32_t lds_stride = 0, lds_nw = 0, lds_nb = 0;
+  size_t lds_bytes = 0;
+  int32_t prec = 0;
+  // byte offsets inside the workspace
+  size_t o_inst, o_win, o_wg, o_ist, o_wst, o_sm, o_xs, o_cfg, o_E, o_att, o_watt, o_spins,
+      o_lng, o_lhi, o_llo, o_H, o_U, o_rep, o_R, o_thermo, o_joins, total;
+};
+
+// Equal-size windows with overlap num/den over bins 0..nbins-1 (Fig. 1a):
+// width W = S/(1+(h-1)(1-o)), lo_i = round(i(1-o)W), hi_i = round((i(1-o)+1)W),
+// half rounded up; computed in integers.
+void equal_windows(int32_t nbins, int32_t h, int32_t on, int32_t od, int32_t* lo, int32_t* hi) {
+  const int64_t S = nbins - 1, d = od - on, D = od + (int64_t)(h - 1) * d;
+  for (int i = 0; i < h; ++i) {
+    lo[i] = (int32_t)((2 * i * d * S + D) / (2 * D));
+    hi[i] = (int32_t)((2 * (i * d + od) * S + D) / (2 * D));
+  }
+}
+
+int check_params(const rewl_params& p) {
+  if (p.model != REWL_ISING && p.model != REWL_POTTS) return REWL_E_INVAL;
+  if (p.L < 2 || p.L > kMaxL) return REWL_E_INVAL;
+  if (p.model == REWL_POTTS && (p.q < 2 || p.q > 127)) return REWL_E_INVAL;
+  if (p.n_windows < 1 || p.walkers_per_window < 1 || p.walkers_per_window > kMaxWalkersPerWindow)
+    return REWL_E_INVAL;
+  if (p.flat_den <= 0 || p.flat_num < 0 || p.flat_num > p.flat_den) return REWL_E_INVAL;
+  if (p.precision != REWL_FP64 && p.precision != REWL_FP32C) return REWL_E_INVAL;
+  if (!(p.lnf_init > 0.0) || !(p.lnf_final > 0.0) || !isfinite(p.lnf_init)) return REWL_E_INVAL;
+  if (p.overlap_den <= 0 || p.overlap_num < 0 || p.overlap_num >= p.overlap_den) return REWL_E_INVAL;
+  return REWL_OK;
+}
+
+int lds_budget_bytes() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+    return v;
+  return 160 * 1024;  // gfx950
+}
+
+int build_layout(const rewl_params* params, int32_t n, const int32_t* wlo, const int32_t* whi,
+                 int lds_budget, Layout& Lo) {
+  if (!params || n < 1) return REWL_E_INVAL;
+  if ((wlo == nullptr) != (whi == nullptr)) return REWL_E_INVAL;
+  Lo = Layout();
+  Lo.prec = params[0].precision;
+  int32_t slot = 0, win = 0, woff = 0, rep = 0, rbase = 0;
+  int64_t spin = 0, lng = 0;
+  int32_t nwmax = 0, nbmax = 0;
+  for (int i = 0; i < n; ++i) {
+    const rewl_params& p = params[i];
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (p.precision != Lo.prec) return REWL_E_INVAL;
+    InstDesc I{};
+    I.model = p.model;
+    I.L = p.L;
+    I.N = p.L * p.L;
+    I.q = p.model == REWL_POTTS ? p.q : 2;
+    I.binw = p.model == REWL_ISING ? 4 : (I.q == 2 ? 2 : 1);
+    I.binw_shift = I.binw == 4 ? 2 : (I.binw == 2 ? 1 : 0);
+    I.emin = -2 * I.N;
+    const int32_t emax = p.model == REWL_ISING ? 2 * I.N : 0;
+    I.nbins = (emax - I.emin) / I.binw + 1;
+    I.h = p.n_windows;
+    I.m = p.walkers_per_window;
+    I.W = I.h * I.m;
+    I.inst = i;
+    I.slot_base = slot;
+    I.win_base = win;
+    I.flat_num = p.flat_num;
+    I.flat_den = p.flat_den;
+    I.npad = (int32_t)align_up((size_t)I.N, 16);
+    I.spin_base = spin;
+    I.lnf_final = p.lnf_final;
+    I.key0 = (uint32_t)p.seed;
+    I.key1 = (uint32_t)(p.seed >> 32);
+    I.invL = 1.0f / (float)p.L;
+    I.r_base = rbase;
+    I.rep_base = rep;
+    std::vector<int32_t> lo(I.h), hi(I.h);
+    if (wlo) {
+      memcpy(lo.data(), wlo + woff, sizeof(int32_t) * I.h);
+      memcpy(hi.data(), whi + woff, sizeof(int32_t) * I.h);
+      woff += I.h;
+    } else {
+      equal_windows(I.nbins, I.h, p.overlap_num, p.overlap_den, lo.data(), hi.data());
+    }
+    I.nbmax = 0;
+    for (int w = 0; w < I.h; ++w) {
+      if (lo[w] < 0 || hi[w] >= I.nbins || hi[w] - lo[w] < 4) return REWL_E_INVAL;
+      if (w > 0 && (lo[w] <= lo[w - 1] || hi[w] <= hi[w - 1] || lo[w] > hi[w - 1])) return REWL_E_INVAL;
+      WinDesc D{};
+      D.lo = lo[w];
+      D.hi = hi[w];
+      D.nb = hi[w] - lo[w] + 1;
+      D.inst = i;
+      D.lng_base = lng;
+      D.u_base = Lo.u_elems;
+      D.rep_off = rep;
+      lng += (int64_t)D.nb * I.m;
+      Lo.u_elems += D.nb;
+      rep += D.nb;
+      I.nbmax = std::max(I.nbmax, D.nb);
+      Lo.win.push_back(D);
+    }
+    nwmax = std::max(nwmax, (I.N + 3) / 4);
+    nbmax = std::max(nbmax, I.nbmax);
+    slot += I.W;
+    win += I.h;
+    spin += (int64_t)I.W * I.npad;
+    rbase += I.nbins;
+    Lo.inst.push_back(I);
+  }
+  Lo.n_slots = slot;
+  Lo.spin_bytes = spin;
+  Lo.lng_elems = lng;
+  Lo.rep_elems = rep;
+  Lo.r_elems = rbase;
+  // Sweep LDS: per lane NW spin words + NB rows of (8 B ln g + 4 B H).
+  Lo.lds_nw = nwmax + (nwmax & 1);
+  Lo.lds_nb = nbmax;
+  const int per_lane = 4 * Lo.lds_nw + 12 * Lo.lds_nb;
+  int G = std::min(kSweepWave, lds_budget / per_lane);
+  if (G < 1) return REWL_E_INVAL;  // one walker does not fit in LDS
+  Lo.lds_stride = G;
+  Lo.lds_bytes = (size_t)G * per_lane;
+  // Workgroups: runs of up to G consecutive walkers of one instance; all
+  // Ising workgroups first.
+  for (int pass = 0; pass < 2; ++pass) {
+    for (const InstDesc& I : Lo.inst) {
+      if ((pass == 0) != (I.model == REWL_ISING)) continue;
+      for (int s0 = 0; s0 < I.W; s0 += G) {
+        WgDesc d{};
+        d.inst = I.inst;
+        d.slot_first = I.slot_base + s0;
+        d.count = std::min(G, I.W - s0);
+        Lo.wg.push_back(d);
+      }
+    }
+    if (pass == 0) Lo.n_wg_ising = (int32_t)Lo.wg.size();
+  }
+  // workspace offsets
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes, kAlign);
+    return at;
+  };
+  const size_t nw = Lo.win.size();
+  Lo.o_inst = take(sizeof(InstDesc) * Lo.inst.size());
+  Lo.o_win = take(sizeof(WinDesc) * nw);
+  Lo.o_wg = take(sizeof(WgDesc) * Lo.wg.size());
+  Lo.o_ist = take(sizeof(InstState) * Lo.inst.size());
+  Lo.o_wst = take(sizeof(WinState) * nw);
+  Lo.o_sm = take(sizeof(int64_t) * kMaxStages * nw);
+  Lo.o_xs = take(sizeof(uint64_t) * 3 * nw);
+  Lo.o_cfg = take(sizeof(int32_t) * slot);
+  Lo.o_E = take(sizeof(int32_t) * slot);
+  Lo.o_att = take(sizeof(uint64_t) * slot);
+  Lo.o_watt = take(sizeof(uint64_t) * slot);
+  Lo.o_spins = take((size_t)spin);
+  if (Lo.prec == REWL_FP64) {
+    Lo.o_lng = take(sizeof(double) * lng);
+    Lo.o_lhi = Lo.o_llo = 0;
+  } else {
+    Lo.o_lng = 0;
+    Lo.o_lhi = take(sizeof(float) * lng);
+    Lo.o_llo = take(sizeof(float) * lng);
+  }
+  Lo.o_H = take(sizeof(uint32_t) * lng);
+  Lo.o_U = take((size_t)Lo.u_elems);
+  Lo.o_rep = take(sizeof(double) * rep);
+  Lo.o_R = take(sizeof(double) * rbase);
+  Lo.o_thermo = take(sizeof(double) * 3 * kMaxTemps);
+  Lo.o_joins = take(sizeof(int32_t) * nw);
+  Lo.total = o;
+  return REWL_OK;
+}
+
+}  // namespace
+
+struct rewl_ctx {
+  Layout lo;
+  std::vector<rewl_params> params;
+  std::vector<int32_t> wlo, whi;
+  unsigned char* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t stream = nullptr;
+  DevPtrs P{};
+  hipGraphExec_t graph = nullptr;
+  int64_t graph_flips = -1;
+  int64_t graph_cycles = 0;
+};
+
+namespace {
+
+template <typename T>
+T* at(rewl_ctx* c, size_t off) {
+  return reinterpret_cast<T*>(c->ws + off);
+}
+
+void fill_ptrs(rewl_ctx* c) {
+  const Layout& L = c->lo;
+  DevPtrs& P = c->P;
+  P.inst = at<InstDesc>(c, L.o_inst);
+  P.win = at<WinDesc>(c, L.o_win);
+  P.wg = at<WgDesc>(c, L.o_wg);
+  P.ist = at<InstState>(c, L.o_ist);
+  P.wst = at<WinState>(c, L.o_wst);
+  P.stage_merge = at<int64_t>(c, L.o_sm);
+  P.xstats = at<uint64_t>(c, L.o_xs);
+  P.cfg = at<int32_t>(c, L.o_cfg);
+  P.E = at<int32_t>(c, L.o_E);
+  P.att = at<uint64_t>(c, L.o_att);
+  P.watt = at<uint64_t>(c, L.o_watt);
+  P.spins = at<int8_t>(c, L.o_spins);
+  P.lng = L.prec == REWL_FP64 ? at<double>(c, L.o_lng) : nullptr;
+  P.lhi = L.prec == REWL_FP32C ? at<float>(c, L.o_lhi) : nullptr;
+  P.llo = L.prec == REWL_FP32C ? at<float>(c, L.o_llo) : nullptr;
+  P.H = at<uint32_t>(c, L.o_H);
+  P.U = at<uint8_t>(c, L.o_U);
+  P.rep = at<double>(c, L.o_rep);
+  P.R = at<double>(c, L.o_R);
+  P.thermo = at<double>(c, L.o_thermo);
+  P.joins = at<int32_t>(c, L.o_joins);
+  P.n_inst = (int32_t)L.inst.size();
+  P.n_win = (int32_t)L.win.size();
+  P.n_slots = L.n_slots;
+  P.n_wg = (int32_t)L.wg.size();
+  P.lds_stride = L.lds_stride;
+  P.lds_nw = L.lds_nw;
+  P.lds_nb = L.lds_nb;
+  P.prec = L.prec;
+}
+
+int hip_rc(hipError_t e) { return e == hipSuccess ? REWL_OK : REWL_E_HIP; }
+
+int sync(rewl_ctx* c) { return hip_rc(hipStreamSynchronize(c->stream)); }
+
+template <typename T>
+int d2h(rewl_ctx* c, T* dst, const void* src, size_t count) {
+  if (!dst || count == 0) return REWL_OK;
+  hipError_t e = hipMemcpyAsync(dst, src, sizeof(T) * count, hipMemcpyDeviceToHost, c->stream);
+  if (e != hipSuccess) return REWL_E_HIP;
+  return sync(c);
+}
+
+int enqueue_cycle(rewl_ctx* c, int64_t flips) {
+  hipError_t e = launch_sweep(c->P, c->lo.n_wg_ising, flips, c->lo.lds_bytes, c->stream);
+  if (e == hipSuccess) e = launch_merge(c->P, c->stream);
+  if (e == hipSuccess) e = launch_exchange(c->P, c->stream);
+  return hip_rc(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t rewl_workspace_bytes(const rewl_params* params, int32_t n, const int32_t* win_lo,
+                            const int32_t* win_hi) {
+  Layout L;
+  if (build_layout(params, n, win_lo, win_hi, lds_budget_bytes(), L) != REWL_OK) return 0;
+  return L.total;
+}
+
+int rewl_init(const rewl_params* params, int32_t n, const int32_t* win_lo, const int32_t* win_hi,
+              void* d_workspace, size_t workspace_bytes, void* stream, rewl_ctx** out) {
+  if (!out || !d_workspace) return REWL_E_INVAL;
+  *out = nullptr;
+  rewl_ctx* c = new (std::nothrow) rewl_ctx();
+  if (!c) return REWL_E_NOMEM;
+  int rc = build_layout(params, n, win_lo, win_hi, lds_budget_bytes(), c->lo);
+  if (rc) {
+    delete c;
+    return rc;
+  }
+  if (workspace_bytes < c->lo.total) {
+    delete c;
+    return REWL_E_NOMEM;
+  }
+  c->params.assign(params, params + n);
+  if (win_lo) {
+    size_t nw = c->lo.win.size();
+    c->wlo.assign(win_lo, win_lo + nw);
+    c->whi.assign(win_hi, win_hi + nw);
+  }
+  c->ws = static_cast<unsigned char*>(d_workspace);
+  c->ws_bytes = workspace_bytes;
+  c->stream = static_cast<hipStream_t>(stream);
+  fill_ptrs(c);
+  const Layout& L = c->lo;
+  hipError_t e = hipMemsetAsync(c->ws, 0, L.total, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->ws + L.o_inst, L.inst.data(), sizeof(InstDesc) * L.inst.size(),
+                       hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->ws + L.o_win, L.win.data(), sizeof(WinDesc) * L.win.size(),
+                       hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->ws + L.o_wg, L.wg.data(), sizeof(WgDesc) * L.wg.size(),
+                       hipMemcpyHostToDevice, c->stream);
+  std::vector<WinState> ws(L.win.size());
+  std::vector<InstState> is(L.inst.size());
+  for (size_t i = 0; i < L.inst.size(); ++i) {
+    const rewl_params& p = params[i];
+    int all = 1;
+    for (int w = 0; w < L.inst[i].h; ++w) {
+      WinState& s = ws[L.inst[i].win_base + w];
+      s.lnf = p.lnf_init;
+      s.stage = 0;
+      s.frozen = p.lnf_init <= p.lnf_final;
+      all &= s.frozen;
+    }
+    is[i].done = all;
+    is[i].error = 0;
+    is[i].done_merge = -1;
+    is[i].merges = 0;
+    is[i].rounds = 0;
+  }
+  std::vector<int64_t> sm((size_t)kMaxStages * L.win.size(), -1);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->ws + L.o_wst, ws.data(), sizeof(WinState) * ws.size(),
+                       hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->ws + L.o_ist, is.data(), sizeof(InstState) * is.size(),
+                       hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->ws + L.o_sm, sm.data(), sizeof(int64_t) * sm.size(),
+                       hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = prepare_sweep_lds(L.lds_bytes);
+  if (e == hipSuccess) e = launch_init(c->P, c->stream);
+  // host vectors above are pageable; make sure the copies finished
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    delete c;
+    return REWL_E_HIP;
+  }
+  *out = c;
+  return REWL_OK;
+}
+
+int rewl_run_sweeps(rewl_ctx* c, int64_t flips) {
+  if (!c || flips < 0) return REWL_E_INVAL;
+  if (flips == 0) return REWL_OK;
+  return hip_rc(launch_sweep(c->P, c->lo.n_wg_ising, flips, c->lo.lds_bytes, c->stream));
+}
+
+int rewl_merge(rewl_ctx* c) {
+  if (!c) return REWL_E_INVAL;
+  return hip_rc(launch_merge(c->P, c->stream));
+}
+
+int rewl_exchange(rewl_ctx* c) {
+  if (!c) return REWL_E_INVAL;
+  return hip_rc(launch_exchange(c->P, c->stream));
+}
+
+int rewl_run_cycles(rewl_ctx* c, int64_t cycles, int64_t flips, int32_t use_graph) {
+  if (!c || cycles < 0 || flips < 0) return REWL_E_INVAL;
+  if (!use_graph) {
+    for (int64_t i = 0; i < cycles; ++i) {
+      int rc = enqueue_cycle(c, flips);
+      if (rc) return rc;
+    }
+    return REWL_OK;
+  }
+  // Capture a batch of cycles once and replay it on the caller's stream.
+  // Capture runs on a private stream (the legacy null stream cannot be
+  // captured); the captured kernels contain no memset/memcpy nodes.
+  const int64_t per_graph = std::min<int64_t>(cycles, 16);
+  if (!c->graph || c->graph_flips != flips || c->graph_cycles != per_graph) {
+    if (c->graph) {
+      (void)hipGraphExecDestroy(c->graph);
+      c->graph = nullptr;
+    }
+    hipStream_t cap = nullptr;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return REWL_E_HIP;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    int rc = e == hipSuccess ? REWL_OK : REWL_E_HIP;
+    hipStream_t user = c->stream;
+    c->stream = cap;
+    for (int64_t i = 0; i < per_graph && rc == REWL_OK; ++i) rc = enqueue_cycle(c, flips);
+    c->stream = user;
+    if (e == hipSuccess) e = hipStreamEndCapture(cap, &g);
+    (void)hipStreamDestroy(cap);
+    if (rc || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return REWL_E_HIP;
+    }
+    e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      c->graph = nullptr;
+      return REWL_E_HIP;
+    }
+    c->graph_flips = flips;
+    c->graph_cycles = per_graph;
+  }
+  int64_t done = 0;
+  while (done + per_graph <= cycles) {
+    if (hipGraphLaunch(c->graph, c->stream) != hipSuccess) return REWL_E_HIP;
+    done += per_graph;
+  }
+  for (; done < cycles; ++done) {
+    int rc = enqueue_cycle(c, flips);
+    if (rc) return rc;
+  }
+  return REWL_OK;
+}
+
+int rewl_status(rewl_ctx* c, int32_t instance, rewl_instance_status* out, int32_t* stage,
+                int32_t* frozen, double* lnf) {
+  if (!c || !out || instance < 0 || instance >= (int32_t)c->lo.inst.size()) return REWL_E_INVAL;
+  const InstDesc& I = c->lo.inst[instance];
+  InstState st;
+  int rc = d2h(c, &st, c->P.ist + instance, 1);
+  if (rc) return rc;
+  std::vector<WinState> ws(I.h);
+  rc = d2h(c, ws.data(), c->P.wst + I.win_base, (size_t)I.h);
+  if (rc) return rc;
+  std::vector<uint64_t> att(I.W);
+  rc = d2h(c, att.data(), c->P.att + I.slot_base, (size_t)I.W);
+  if (rc) return rc;
+  out->done = st.done;
+  out->error = st.error;
+  out->done_merge = st.done_merge;
+  out->merges = st.merges;
+  out->rounds = st.rounds;
+  uint64_t a = 0;
+  for (uint64_t v : att) a += v;
+  out->attempts = a;
+  for (int w = 0; w < I.h; ++w) {
+    if (stage) stage[w] = ws[w].stage;
+    if (frozen) frozen[w] = ws[w].frozen;
+    if (lnf) lnf[w] = ws[w].lnf;
+  }
+  return REWL_OK;
+}
+
+int rewl_running(rewl_ctx* c, int32_t* n_running) {
+  if (!c || !n_running) return REWL_E_INVAL;
+  std::vector<InstState> st(c->lo.inst.size());
+  int rc = d2h(c, st.data(), c->P.ist, st.size());
+  if (rc) return rc;
+  int32_t r = 0;
+  for (const InstState& s : st) r += (s.done || s.error) ? 0 : 1;
+  *n_running = r;
+  return REWL_OK;
+}
+
+int rewl_get_geometry(rewl_ctx* c, int32_t instance, int32_t* N, int32_t* nbins, int32_t* binw,
+                      int32_t* emin, int32_t* h, int32_t* m, int32_t* first_slot, int32_t* win_lo,
+                      int32_t* win_hi) {
+  if (!c || instance < 0 || instance >= (int32_t)c->lo.inst.size()) return REWL_E_INVAL;
+  const InstDesc& I = c->lo.inst[instance];
+  if (N) *N = I.N;
+  if (nbins) *nbins = I.nbins;
+  if (binw) *binw = I.binw;
+  if (emin) *emin = I.emin;
+  if (h) *h = I.h;
+  if (m) *m = I.m;
+  if (first_slot) *first_slot = I.slot_base;
+  for (int w = 0; w < I.h; ++w) {
+    if (win_lo) win_lo[w] = c->lo.win[I.win_base + w].lo;
+    if (win_hi) win_hi[w] = c->lo.win[I.win_base + w].hi;
+  }
+  return REWL_OK;
+}
+
+int rewl_get_walker(rewl_ctx* c, int32_t instance, int32_t slot, int8_t* spins, int32_t* energy,
+                    uint32_t* H, double* lng, uint64_t* attempts, int32_t* config_id) {
+  if (!c || instance < 0 || instance >= (int32_t)c->lo.inst.size()) return REWL_E_INVAL;
+  const InstDesc& I = c->lo.inst[instance];
+  if (slot < 0 || slot >= I.W) return REWL_E_INVAL;
+  const int g = I.slot_base + slot;
+  const WinDesc& W = c->lo.win[I.win_base + slot / I.m];
+  const int64_t base = W.lng_base + (int64_t)(slot % I.m) * W.nb;
+  int32_t cfg = 0;
+  int rc = d2h(c, &cfg, c->P.cfg + g, 1);
+  if (rc) return rc;
+  if (config_id) *config_id = cfg - I.slot_base;
+  if (spins) rc = d2h(c, spins, c->P.spins + I.spin_base + (int64_t)(cfg - I.slot_base) * I.npad, (size_t)I.N);
+  if (!rc && energy) rc = d2h(c, energy, c->P.E + g, 1);
+  if (!rc && attempts) rc = d2h(c, attempts, c->P.att + g, 1);
+  if (!rc && H) rc = d2h(c, H, c->P.H + base, (size_t)W.nb);
+  if (!rc && lng) {
+    if (c->lo.prec == REWL_FP64) {
+      rc = d2h(c, lng, c->P.lng + base, (size_t)W.nb);
+    } else {
+      std::vector<float> hi(W.nb), lo(W.nb);
+      rc = d2h(c, hi.data(), c->P.lhi + base, (size_t)W.nb);
+      if (!rc) rc = d2h(c, lo.data(), c->P.llo + base, (size_t)W.nb);
+      for (int j = 0; j < W.nb && !rc; ++j) lng[j] = (double)hi[j] + (double)lo[j];
+    }
+  }
+  return rc;
+}
+
+int rewl_get_walker_f32(rewl_ctx* c, int32_t instance, int32_t slot, float* hi, float* lo) {
+  if (!c || instance < 0 || instance >= (int32_t)c->lo.inst.size()) return REWL_E_INVAL;
+  if (c->lo.prec != REWL_FP32C) return REWL_E_STATE;
+  const InstDesc& I = c->lo.inst[instance];
+  if (slot < 0 || slot >= I.W) return REWL_E_INVAL;
+  const WinDesc& W = c->lo.win[I.win_base + slot / I.m];
+  const int64_t base = W.lng_base + (int64_t)(slot % I.m) * W.nb;
+  int rc = d2h(c, hi, c->P.lhi + base, (size_t)W.nb);
+  if (!rc) rc = d2h(c, lo, c->P.llo + base, (size_t)W.nb);
+  return rc;
+}
+
+int rewl_get_visited(rewl_ctx* c, int32_t instance, int32_t window, uint8_t* mask) {
+  if (!c || !mask || instance < 0 || instance >= (int32_t)c->lo.inst.size()) return REWL_E_INVAL;
+  const InstDesc& I = c->lo.inst[instance];
+  if (window < 0 || window >= I.h) return REWL_E_INVAL;
+  const WinDesc& W = c->lo.win[I.win_base + window];
+  return d2h(c, mask, c->P.U + W.u_base, (size_t)W.nb);
+}
+
+int rewl_get_exchange_stats(rewl_ctx* c, int32_t instance, uint64_t* tries, uint64_t* in_range,
+                            uint64_t* accepts) {
+  if (!c || instance < 0 || instance >= (int32_t)c->lo.inst.size()) return REWL_E_INVAL;
+  const InstDesc& I = c->lo.inst[instance];
+  std::vector<uint64_t> xs(3 * (size_t)I.h);
+  int rc = d2h(c, xs.data(), c->P.xstats + 3 * (size_t)I.win_base, xs.size());
+  if (rc) return rc;
+  for (int w = 0; w < I.h; ++w) {
+    if (tries) tries[w] = xs[3 * w];
+    if (in_range) in_range[w] = xs[3 * w + 1];
+    if (accepts) accepts[w] = xs[3 * w + 2];
+  }
+  return REWL_OK;
+}
+
+int rewl_get_lng(rewl_ctx* c, int32_t instance, int32_t which, double* out, int32_t capacity,
+                 int32_t* n_bins_out, int32_t* joins) {
+  if (!c || !out || instance < 0 || instance >= (int32_t)c->lo.inst.size()) return REWL_E_INVAL;
+  if (which != 0 && which != 1) return REWL_E_INVAL;
+  const InstDesc& I = c->lo.inst[instance];
+  if (n_bins_out) *n_bins_out = I.nbins;
+  if (capacity < I.nbins) return REWL_E_INVAL;
+  int rc = hip_rc(launch_join(c->P, instance, which == 0, c->stream));
+  if (rc) return rc;
+  rc = d2h(c, out, c->P.R + I.r_base, (size_t)I.nbins);
+  if (!rc && joins && I.h > 1) rc = d2h(c, joins, c->P.joins + I.win_base + 1, (size_t)(I.h - 1));
+  return rc;
+}
+
+int rewl_thermo(rewl_ctx* c, int32_t instance, const double* T, int32_t nT, double* E_mean,
+                double* C_v) {
+  if (!c || !T || instance < 0 || instance >= (int32_t)c->lo.inst.size()) return REWL_E_INVAL;
+  if (nT < 1 || nT > kMaxTemps) return REWL_E_INVAL;
+  for (int i = 0; i < nT; ++i)
+    if (!(T[i] > 0.0)) return REWL_E_INVAL;
+  int rc = hip_rc(launch_join(c->P, instance, 1, c->stream));
+  if (rc) return rc;
+  rc = hip_rc(hipMemcpyAsync(c->P.thermo, T, sizeof(double) * nT, hipMemcpyHostToDevice, c->stream));
+  if (rc) return rc;
+  rc = hip_rc(launch_thermo(c->P, instance, nT, c->stream));
+  if (rc) return rc;
+  rc = d2h(c, E_mean, c->P.thermo + kMaxTemps, (size_t)nT);
+  if (!rc) rc = d2h(c, C_v, c->P.thermo + 2 * kMaxTemps, (size_t)nT);
+  return rc;
+}
+
+int rewl_checkpoint(rewl_ctx* c, void* buf, size_t cap, size_t* used) {
+  if (!c) return REWL_E_INVAL;
+  const size_t need = 2 * sizeof(uint64_t) + c->lo.total;
+  if (used) *used = need;
+  if (!buf) return REWL_OK;
+  if (cap < need) return REWL_E_NOMEM;
+  uint64_t hdr[2] = {kCkptMagic, (uint64_t)c->lo.total};
+  memcpy(buf, hdr, sizeof(hdr));
+  return d2h(c, static_cast<unsigned char*>(buf) + sizeof(hdr), c->ws, c->lo.total);
+}
+
+int rewl_restore(rewl_ctx* c, const void* buf, size_t n) {
+  if (!c || !buf) return REWL_E_INVAL;
+  uint64_t hdr[2];
+  if (n < sizeof(hdr)) return REWL_E_FORMAT;
+  memcpy(hdr, buf, sizeof(hdr));
+  if (hdr[0] != kCkptMagic || hdr[1] != (uint64_t)c->lo.total || n != sizeof(hdr) + c->lo.total)
+    return REWL_E_FORMAT;
+  // The descriptors in the blob must describe this context's layout.
+  const unsigned char* p = static_cast<const unsigned char*>(buf) + sizeof(hdr);
+  const Layout& L = c->lo;
+  if (memcmp(p + L.o_inst, L.inst.data(), sizeof(InstDesc) * L.inst.size()) != 0 ||
+      memcmp(p + L.o_win, L.win.data(), sizeof(WinDesc) * L.win.size()) != 0 ||
+      memcmp(p + L.o_wg, L.wg.data(), sizeof(WgDesc) * L.wg.size()) != 0)
+    return REWL_E_FORMAT;
+  int rc = hip_rc(hipMemcpyAsync(c->ws, p, L.total, hipMemcpyHostToDevice, c->stream));
+  if (!rc) rc = sync(c);
+  return rc;
+}
+
+int rewl_destroy(rewl_ctx* c) {
+  if (!c) return REWL_E_INVAL;
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  delete c;
+  return REWL_OK;
+}
+
+const char* rewl_strerror(int code) {
+  switch (code) {
+    case REWL_OK: return "ok";
+    case REWL_E_INVAL: return "invalid argument";
+    case REWL_E_NOMEM: return "workspace or buffer too small";
+    case REWL_E_HIP: return "HIP runtime error";
+    case REWL_E_NONFINITE: return "non-finite ln g";
+    case REWL_E_OVERFLOW: return "histogram overflow";
+    case REWL_E_STATE: return "call not valid in this state";
+    case REWL_E_WARMUP: return "walker could not reach its window";
+    case REWL_E_FORMAT: return "checkpoint does not match this context";
+    default: return "unknown error";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,66 @@
+"""Helpers for GPU-vs-oracle parity tests: build the same REWL instance on
+both sides and compare their complete logical state."""
+import numpy as np
+
+from oracle import oracle as O
+from paper_1402_2328_amd import workloads
+
+
+def oracle_sim(cfg, instance=0, windows=None):
+    return O.Sim(windows=windows, model=cfg["model"], L=cfg["L"], q=cfg["q"], n_windows=cfg["n_windows"],
+                 overlap=tuple(cfg["overlap"]), walkers_per_window=cfg["walkers_per_window"],
+                 flat=tuple(cfg["flat"]), lnf_init=cfg["lnf_init"], lnf_final=cfg["lnf_final"],
+                 flips_per_exchange=cfg["flips_per_exchange"], seed=cfg["seed"],
+                 precision=cfg["precision"], instance=instance)
+
+
+def gpu_context(cfgs, windows=None):
+    from paper_1402_2328_amd import rewl
+    return rewl.Context([workloads.rewl_params_of(c) for c in cfgs], windows=windows)
+
+
+def oracle_cycle(sim, flips):
+    sim.sweep(flips)
+    sim.merge()
+    sim.exchange()
+
+
+def compare_state(ctx, instance, sim, slots=None, windows=True):
+    """Assert the GPU instance and the oracle hold identical state.
+
+    Walker-level: spins of the carried configuration, energy, H, ln g bits
+    (FP64, or both two-float parts), attempt counter, configuration identity.
+    Window-level: ln f, stage, frozen flag, visited union.  Instance-level:
+    finished flag, merge and round counters, exchange statistics.
+    """
+    g = ctx.geometry[instance]
+    W = g["h"] * g["m"]
+    slots = range(W) if slots is None else slots
+    for slot in slots:
+        a, b = ctx.get_walker(instance, slot), sim.walker(slot)
+        tag = f"instance {instance} slot {slot}"
+        assert a["E"] == b["E"], tag
+        assert a["attempts"] == b["attempts"], tag
+        assert a["config"] == b["config"], tag
+        assert np.array_equal(a["spins"], b["spins"]), tag
+        assert np.array_equal(a["H"], b["H"]), tag
+        if "lng_hi" in a:
+            assert np.array_equal(a["lng_hi"].view(np.uint32), b["lng_hi"].view(np.uint32)), tag
+            assert np.array_equal(a["lng_lo"].view(np.uint32), b["lng_lo"].view(np.uint32)), tag
+        else:
+            assert np.array_equal(a["lng"].view(np.uint64), b["lng"].view(np.uint64)), tag
+    if not windows:
+        return
+    st = ctx.status(instance)
+    os_ = sim.status()
+    assert st["done"] == os_["done"]
+    assert st["merges"] == os_["merges"] and st["rounds"] == os_["rounds"]
+    assert st["done_merge"] == os_["done_merge"]
+    for w in range(g["h"]):
+        ow = sim.window(w)
+        assert st["stage"][w] == ow["stage"] and st["frozen"][w] == ow["frozen"], w
+        assert st["lnf"][w] == ow["lnf"], w
+        assert np.array_equal(ctx.get_visited(instance, w), ow["U"]), w
+    t, r, a = ctx.get_exchange_stats(instance)
+    ot, orr, oa = sim.exchange_stats()
+    assert np.array_equal(t, ot) and np.array_equal(r, orr) and np.array_equal(a, oa)

@@ -1,0 +1,67 @@
+"""The C-ABI library loads and exports what include/rewl.h declares, and its
+host-side validation works without a GPU (no compute calls here)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1402_2328_amd import rewl, workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "rewl.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rewl_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    decl = declared_functions()
+    assert decl == sorted(rewl.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = rewl.lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_strerror_names_codes():
+    lib = rewl.lib()
+    for code in range(-8, 1):
+        assert lib.rewl_strerror(code).decode() == rewl.ERRORS[code]
+
+
+@pytest.mark.parametrize("bad", [dict(L=1), dict(L=65), dict(n_windows=0), dict(walkers_per_window=0),
+                                 dict(walkers_per_window=65), dict(flat=(6, 5)), dict(lnf_init=0.0),
+                                 dict(overlap=(4, 4)), dict(n_windows=400)])
+def test_workspace_bytes_rejects_bad_parameters(bad):
+    cfg = dict(workloads.CFG1)
+    cfg.update(bad)
+    assert rewl.rewl_workspace_bytes([workloads.rewl_params_of(cfg)]) == 0
+
+
+def test_workspace_bytes_for_configs():
+    for cfg in (workloads.CFG1, workloads.CFG2, workloads.CFG3, workloads.CFG4):
+        n = rewl.rewl_workspace_bytes([workloads.rewl_params_of(cfg)])
+        assert 0 < n < 64 * 2 ** 20
+    p = [workloads.rewl_params_of(workloads.CFG2)]
+    assert rewl.rewl_workspace_bytes(p * 4) > 2 * rewl.rewl_workspace_bytes(p)
+
+
+def test_mixed_precision_batch_rejected():
+    a = dict(workloads.CFG1)
+    b = dict(workloads.CFG1, precision=workloads.FP32C)
+    assert rewl.rewl_workspace_bytes([workloads.rewl_params_of(a), workloads.rewl_params_of(b)]) == 0
+
+
+def test_explicit_windows_validated():
+    p = [workloads.rewl_params_of(workloads.CFG1)]
+    good = [([0, 9, 18, 27], [37, 46, 55, 64])]
+    assert rewl.rewl_workspace_bytes(p, good) > 0
+    for bad in ([([0, 9, 18, 27], [37, 46, 55, 65])],        # beyond the range
+                [([0, 40, 41, 42], [37, 46, 55, 64])],       # no overlap between 0 and 1
+                [([0, 9, 9, 27], [37, 46, 55, 64])]):        # not increasing
+        assert rewl.rewl_workspace_bytes(p, bad) == 0

@@ -1,0 +1,169 @@
+"""GPU parity: the HIP path (through the C-ABI) against the oracle, bit for bit.
+
+Integer state (spins, energies, histograms, counters, configuration
+identities) and ln g bits must be identical after every checked segment; the
+joined ln g before normalisation must be identical too; after normalisation
+(which uses the platform's exp/log) it must agree to 1e-12 absolute.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1402_2328_amd import workloads as WL
+from tests.parity import compare_state, gpu_context, oracle_cycle, oracle_sim
+
+pytestmark = pytest.mark.gpu
+
+SMALL = {
+    "ising_L8_h4_m2": WL.config(WL.ISING, 8, n_windows=4, walkers_per_window=2, lnf_final=1e-6,
+                                flips=500, seed=3),
+    "ising_L6_h3_m3": WL.config(WL.ISING, 6, n_windows=3, walkers_per_window=3,
+                                    lnf_final=1e-5, flips=250, seed=11),
+    "ising_L16_h5_m4": WL.config(WL.ISING, 16, n_windows=5, walkers_per_window=4, flips=2000,
+                                 seed=2),
+    "ising_L12_h1_m1": WL.config(WL.ISING, 12, n_windows=1, walkers_per_window=1, flips=3000,
+                                 seed=9),
+    "potts_q5_L12_h9_m7_ragged": WL.config(WL.POTTS, 12, q=5, n_windows=9, walkers_per_window=7,
+                                           flips=1500, seed=12),
+    "potts_q10_L8_h4_m4": WL.config(WL.POTTS, 8, q=10, n_windows=4, walkers_per_window=4,
+                                    flips=1000, seed=4),
+    "potts_q2_L8_h3_m2": WL.config(WL.POTTS, 8, q=2, n_windows=3, walkers_per_window=2,
+                                   flips=700, seed=5),
+    "potts_q3_L10_h6_m3": WL.config(WL.POTTS, 10, q=3, n_windows=6, walkers_per_window=3,
+                                    flips=900, seed=6),
+    "ising_L8_fp32c": WL.config(WL.ISING, 8, n_windows=4, walkers_per_window=2, lnf_final=1e-6,
+                                flips=500, seed=3, precision=WL.FP32C),
+    "potts_q10_L8_fp32c": WL.config(WL.POTTS, 8, q=10, n_windows=4, walkers_per_window=4,
+                                    flips=1000, seed=4, precision=WL.FP32C),
+}
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_initial_state_and_segments_match(name):
+    cfg = SMALL[name]
+    ctx = gpu_context([cfg])
+    sim = oracle_sim(cfg)
+    print(f"[parity] {name}: init", flush=True)
+    compare_state(ctx, 0, sim)
+    F = cfg["flips_per_exchange"]
+    for seg in (1, 2, 10, 40):
+        for _ in range(seg):
+            ctx.run_sweeps(F)
+            ctx.merge()
+            ctx.exchange()
+            oracle_cycle(sim, F)
+        print(f"[parity] {name}: +{seg} cycles", flush=True)
+        compare_state(ctx, 0, sim)
+
+
+@pytest.mark.parametrize("name", ["ising_L8_h4_m2", "potts_q2_L8_h3_m2", "ising_L8_fp32c"])
+def test_full_run_to_convergence_matches(name):
+    cfg = SMALL[name]
+    ctx = gpu_context([cfg])
+    sim = oracle_sim(cfg)
+    F = cfg["flips_per_exchange"]
+    n = ctx.run_to_convergence(F, cycles_per_check=200)
+    ocycles = sim.run(10 ** 8)
+    st = ctx.status(0)
+    assert st["done"] == 1 and sim.status()["done"] == 1
+    assert st["done_merge"] == sim.status()["done_merge"]
+    assert n >= ocycles
+    compare_state(ctx, 0, sim)
+    raw_g, joins_g = ctx.get_lng(0, normalise=False)
+    raw_o, joins_o = sim.join(normalise=False)
+    assert np.array_equal(joins_g, joins_o)
+    assert np.array_equal(raw_g.view(np.uint64), raw_o.view(np.uint64))
+    nrm_g, _ = ctx.get_lng(0)
+    nrm_o, _ = sim.join()
+    fin = np.isfinite(nrm_o)
+    assert np.array_equal(np.isfinite(nrm_g), fin)
+    assert np.max(np.abs(nrm_g[fin] - nrm_o[fin])) < 1e-12
+
+
+def test_instances_in_a_batch_match_standalone_oracles():
+    cfgs = [SMALL["ising_L8_h4_m2"], SMALL["ising_L16_h5_m4"], SMALL["potts_q10_L8_h4_m4"],
+            SMALL["potts_q2_L8_h3_m2"], SMALL["ising_L8_h4_m2"]]
+    ctx = gpu_context(cfgs)
+    sims = [oracle_sim(c, instance=i) for i, c in enumerate(cfgs)]
+    F = 800
+    for _ in range(12):
+        ctx.run_sweeps(F)
+        ctx.merge()
+        ctx.exchange()
+        for s in sims:
+            oracle_cycle(s, F)
+    for i, s in enumerate(sims):
+        compare_state(ctx, i, s)
+
+
+def test_graph_replay_equals_eager():
+    cfg = SMALL["potts_q10_L8_h4_m4"]
+    a, b = gpu_context([cfg]), gpu_context([cfg])
+    a.run_cycles(37, 1000, use_graph=False)
+    for _ in range(3):          # replays with eager work and syncs in between
+        b.run_cycles(12, 1000, use_graph=True)
+        b.status(0)
+    b.run_cycles(1, 1000, use_graph=False)
+    sim = oracle_sim(cfg)
+    for _ in range(37):
+        oracle_cycle(sim, 1000)
+    compare_state(a, 0, sim)
+    compare_state(b, 0, sim)
+
+
+def test_checkpoint_restore_continues_bit_exactly():
+    cfg = SMALL["ising_L16_h5_m4"]
+    a = gpu_context([cfg])
+    a.run_cycles(10, 2000)
+    blob = a.checkpoint()
+    a.run_cycles(10, 2000)
+    b = gpu_context([cfg])
+    b.restore(blob)
+    b.run_cycles(10, 2000)
+    for slot in range(20):
+        x, y = a.get_walker(0, slot), b.get_walker(0, slot)
+        assert np.array_equal(x["spins"], y["spins"]) and np.array_equal(x["lng"], y["lng"])
+        assert np.array_equal(x["H"], y["H"]) and x["attempts"] == y["attempts"]
+    # a blob from another configuration is refused
+    c = gpu_context([SMALL["ising_L8_h4_m2"]])
+    with pytest.raises(Exception):
+        c.restore(blob)
+
+
+def test_thermo_matches_oracle():
+    cfg = SMALL["ising_L8_h4_m2"]
+    ctx = gpu_context([cfg])
+    sim = oracle_sim(cfg)
+    ctx.run_to_convergence(500, cycles_per_check=200)
+    sim.run(10 ** 8)
+    T = np.linspace(1.0, 4.0, 61)
+    Eg, Cg = ctx.thermo(T)
+    R, _ = sim.join()
+    Eo, Co = O.thermo(R, -128, 4, T)
+    assert np.allclose(Eg, Eo, rtol=1e-11, atol=1e-9)
+    assert np.allclose(Cg, Co, rtol=1e-10, atol=1e-9)
+
+
+def test_zero_flips_is_a_no_op_and_negative_is_rejected():
+    cfg = SMALL["ising_L8_h4_m2"]
+    ctx = gpu_context([cfg])
+    sim = oracle_sim(cfg)
+    ctx.run_sweeps(0)
+    compare_state(ctx, 0, sim)
+    with pytest.raises(Exception):
+        ctx.run_sweeps(-1)
+
+
+def test_unreachable_window_is_reported_on_both_sides():
+    # odd L = 5: frustration caps the Ising energy at +30, so a window over
+    # E in [34, 50] (bins 21..25) can never be entered
+    cfg = WL.config(WL.ISING, 5, n_windows=3, walkers_per_window=1, flips=100, seed=1)
+    win = ([0, 10, 21], [12, 22, 25])
+    sim = oracle_sim(cfg, windows=win)
+    assert not sim.warm_ok
+    ctx = gpu_context([cfg], windows=[win])
+    assert ctx.status(0)["error"] == -7
+    ctx.run_cycles(3, 100)             # a failed instance is never advanced
+    st = ctx.status(0)
+    assert st["merges"] == 0 and st["rounds"] == 0 and st["attempts"] == 0
+    assert ctx.running() == 0
