@@ -88,9 +88,10 @@ def main():
     prec = WL.FP64 if a.precision == "fp64" else WL.FP32C
     cfg = dict(WL.CFG2, precision=prec, flips_per_exchange=a.flips)
     one = [WL.rewl_params_of(cfg)]
-    R = a.replicas if a.replicas > 0 else 170
+    R = a.replicas if a.replicas > 0 else WL.bench_replicas(cfg)
     params = one * R
     ctx = rewl.Context(params)
+    plan = ctx.set_launch()
     W = R * cfg["n_windows"] * cfg["walkers_per_window"]
     stream = ctx.stream
 
@@ -135,7 +136,7 @@ def main():
         "config": {"workload": f"2D Ising L=32 REWL, 16 windows x 8 walkers, 75% overlap, "
                                f"flatness 0.8, F={a.flips} flips per exchange, x{R} independent "
                                f"instances", "replicas": R, "walkers": W, "flips": a.flips,
-                   "precision": a.precision},
+                   "precision": a.precision, "launch": plan},
         "roofline": {"bound": "alu", "achieved": achieved_valu / 1e12, "peak": PEAK_VALU / 1e12,
                      "unit": "Tlane-op/s", "frac": achieved_valu / PEAK_VALU, "traffic": None,
                      "kernel": "k_sweep", "kernel_ms": sweep_ms,

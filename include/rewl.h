@@ -109,6 +109,16 @@ int rewl_init(const rewl_params* params, int32_t n_instances,
  * ln g or H.  Errors: INVAL (flips < 0), HIP. */
 int rewl_run_sweeps(rewl_ctx* ctx, int64_t flips);
 
+/* Chooses the sweep's launch shape: page_bins ln g / H bins of each walker
+ * kept in LDS (the rest of a larger window stays in device memory and the
+ * page follows the walker) and walkers_per_group walkers per 64-lane
+ * workgroup; 0 picks the default (the largest page that lets four
+ * workgroups share a compute unit).  Results do not depend on the shape.
+ * out: NULL or 4 entries {page_bins, walkers_per_group, LDS bytes per
+ * workgroup, workgroups}.  Synchronises.  Errors: INVAL (shape does not fit
+ * in LDS), HIP. */
+int rewl_set_launch(rewl_ctx* ctx, int32_t page_bins, int32_t walkers_per_group, int32_t* out);
+
 /* Enqueues the flatness test and in-window merge for every non-frozen window
  * (Sec. 2): when all m walkers of a window are flat at this check, their ln g
  * are averaged (pairwise sum in walker order, divided by m), H is reset and

@@ -28,16 +28,14 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 struct Layout {
   std::vector<InstDesc> inst;
   std::vector<WinDesc> win;
-  std::vector<WgDesc> wg;
-  int32_t n_wg_ising = 0;
   int32_t n_slots = 0;
   int64_t spin_bytes = 0;
   int64_t lng_elems = 0;
   int32_t u_elems = 0;
   int32_t rep_elems = 0;
   int32_t r_elems = 0;
-  int32_t lds_stride = 0, lds_nw = 0, lds_nb = 0;
-  size_t lds_bytes = 0;
+  int32_t lat_words = 0;  // largest per-walker lattice in the sweep's LDS format, 32-bit words
+  int32_t nb_max = 0;     // largest window, bins
   int32_t prec = 0;
   // byte offsets inside the workspace
   size_t o_inst, o_win, o_wg, o_ist, o_wst, o_sm, o_xs, o_cfg, o_E, o_att, o_watt, o_spins,
@@ -142,7 +140,10 @@ int build_layout(const rewl_params* params, int32_t n, const int32_t* wlo, const
       I.nbmax = std::max(I.nbmax, D.nb);
       Lo.win.push_back(D);
     }
-    nwmax = std::max(nwmax, (I.N + 3) / 4);
+    // sweep LDS lattice: Ising bit rows (1 word per row for L <= 32, else 2),
+    // Potts bytes
+    const int lw = I.model == REWL_ISING ? I.L * (I.L <= 32 ? 1 : 2) : (I.N + 3) / 4;
+    nwmax = std::max(nwmax, lw);
     nbmax = std::max(nbmax, I.nbmax);
     slot += I.W;
     win += I.h;
@@ -155,29 +156,8 @@ int build_layout(const rewl_params* params, int32_t n, const int32_t* wlo, const
   Lo.lng_elems = lng;
   Lo.rep_elems = rep;
   Lo.r_elems = rbase;
-  // Sweep LDS: per lane NW spin words + NB rows of (8 B ln g + 4 B H).
-  Lo.lds_nw = nwmax + (nwmax & 1);
-  Lo.lds_nb = nbmax;
-  const int per_lane = 4 * Lo.lds_nw + 12 * Lo.lds_nb;
-  int G = std::min(kSweepWave, lds_budget / per_lane);
-  if (G < 1) return REWL_E_INVAL;  // one walker does not fit in LDS
-  Lo.lds_stride = G;
-  Lo.lds_bytes = (size_t)G * per_lane;
-  // Workgroups: runs of up to G consecutive walkers of one instance; all
-  // Ising workgroups first.
-  for (int pass = 0; pass < 2; ++pass) {
-    for (const InstDesc& I : Lo.inst) {
-      if ((pass == 0) != (I.model == REWL_ISING)) continue;
-      for (int s0 = 0; s0 < I.W; s0 += G) {
-        WgDesc d{};
-        d.inst = I.inst;
-        d.slot_first = I.slot_base + s0;
-        d.count = std::min(G, I.W - s0);
-        Lo.wg.push_back(d);
-      }
-    }
-    if (pass == 0) Lo.n_wg_ising = (int32_t)Lo.wg.size();
-  }
+  Lo.lat_words = nwmax + (nwmax & 1);
+  Lo.nb_max = nbmax;
   // workspace offsets
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -188,7 +168,7 @@ int build_layout(const rewl_params* params, int32_t n, const int32_t* wlo, const
   const size_t nw = Lo.win.size();
   Lo.o_inst = take(sizeof(InstDesc) * Lo.inst.size());
   Lo.o_win = take(sizeof(WinDesc) * nw);
-  Lo.o_wg = take(sizeof(WgDesc) * Lo.wg.size());
+  Lo.o_wg = take(sizeof(WgDesc) * (size_t)slot);  // room for one walker per workgroup
   Lo.o_ist = take(sizeof(InstState) * Lo.inst.size());
   Lo.o_wst = take(sizeof(WinState) * nw);
   Lo.o_sm = take(sizeof(int64_t) * kMaxStages * nw);
@@ -216,10 +196,66 @@ int build_layout(const rewl_params* params, int32_t n, const int32_t* wlo, const
   return REWL_OK;
 }
 
+// Sweep launch plan: walkers per workgroup (G, one wavefront), ln g page
+// rows (P) and the workgroup table.  Per lane the sweep needs
+// 4 * lat_words + 12 * P bytes of LDS.  By default P is the largest page
+// that still lets T = 4 (else 3, 2, 1) full workgroups share a CU, as long
+// as that page holds min(nb_max, 32) bins.
+struct LaunchPlan {
+  int32_t G = 0, P = 0;
+  size_t lds_bytes = 0;
+  std::vector<WgDesc> wg;
+  int32_t class_count[3] = {0, 0, 0};
+};
+
+int plan_launch(const Layout& Lo, int lds_budget, int page_req, int g_req, LaunchPlan& pl) {
+  pl = LaunchPlan();
+  const int lat = 4 * Lo.lat_words;
+  int P = 0, G = kSweepWave;
+  if (page_req > 0) {
+    P = std::min(page_req, Lo.nb_max);
+  } else {
+    const int want = std::min(Lo.nb_max, 32);
+    for (int T = 4; T >= 1 && P == 0; --T) {
+      const int p = (lds_budget / (kSweepWave * T) - lat) / 12;
+      if (p >= want) P = std::min(p, Lo.nb_max);
+    }
+    if (P == 0) P = want;
+  }
+  // the page ring must hold bin +- 2D (D = 4 for q >= 3 Potts, else 2)
+  bool potts3 = false;
+  for (const InstDesc& I : Lo.inst) potts3 |= (I.model == REWL_POTTS && I.q >= 3);
+  const int pmin = potts3 ? 17 : 9;
+  if (P < pmin && P < Lo.nb_max) P = std::min(pmin, Lo.nb_max);
+  if (g_req > 0) G = std::min(g_req, kSweepWave);
+  G = std::min(G, lds_budget / (lat + 12 * P));
+  if (G < 1) return REWL_E_INVAL;
+  pl.G = G;
+  pl.P = P;
+  pl.lds_bytes = (size_t)G * (lat + 12 * P);
+  for (int cls = 0; cls < 3; ++cls) {
+    const size_t before = pl.wg.size();
+    for (const InstDesc& I : Lo.inst) {
+      const int c = I.model == REWL_POTTS ? 2 : (I.L <= 32 ? 0 : 1);
+      if (c != cls) continue;
+      for (int s0 = 0; s0 < I.W; s0 += G) {
+        WgDesc d{};
+        d.inst = I.inst;
+        d.slot_first = I.slot_base + s0;
+        d.count = std::min(G, I.W - s0);
+        pl.wg.push_back(d);
+      }
+    }
+    pl.class_count[cls] = (int32_t)(pl.wg.size() - before);
+  }
+  return REWL_OK;
+}
+
 }  // namespace
 
 struct rewl_ctx {
   Layout lo;
+  LaunchPlan plan;
   std::vector<rewl_params> params;
   std::vector<int32_t> wlo, whi;
   unsigned char* ws = nullptr;
@@ -265,10 +301,10 @@ void fill_ptrs(rewl_ctx* c) {
   P.n_inst = (int32_t)L.inst.size();
   P.n_win = (int32_t)L.win.size();
   P.n_slots = L.n_slots;
-  P.n_wg = (int32_t)L.wg.size();
-  P.lds_stride = L.lds_stride;
-  P.lds_nw = L.lds_nw;
-  P.lds_nb = L.lds_nb;
+  P.n_wg = (int32_t)c->plan.wg.size();
+  P.lds_stride = c->plan.G;
+  P.lds_nw = L.lat_words;
+  P.page_bins = c->plan.P;
   P.prec = L.prec;
 }
 
@@ -285,7 +321,7 @@ int d2h(rewl_ctx* c, T* dst, const void* src, size_t count) {
 }
 
 int enqueue_cycle(rewl_ctx* c, int64_t flips) {
-  hipError_t e = launch_sweep(c->P, c->lo.n_wg_ising, flips, c->lo.lds_bytes, c->stream);
+  hipError_t e = launch_sweep(c->P, c->plan.class_count, flips, c->plan.lds_bytes, c->stream);
   if (e == hipSuccess) e = launch_merge(c->P, c->stream);
   if (e == hipSuccess) e = launch_exchange(c->P, c->stream);
   return hip_rc(e);
@@ -309,6 +345,7 @@ int rewl_init(const rewl_params* params, int32_t n, const int32_t* win_lo, const
   rewl_ctx* c = new (std::nothrow) rewl_ctx();
   if (!c) return REWL_E_NOMEM;
   int rc = build_layout(params, n, win_lo, win_hi, lds_budget_bytes(), c->lo);
+  if (!rc) rc = plan_launch(c->lo, lds_budget_bytes(), 0, 0, c->plan);
   if (rc) {
     delete c;
     return rc;
@@ -336,7 +373,7 @@ int rewl_init(const rewl_params* params, int32_t n, const int32_t* win_lo, const
     e = hipMemcpyAsync(c->ws + L.o_win, L.win.data(), sizeof(WinDesc) * L.win.size(),
                        hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(c->ws + L.o_wg, L.wg.data(), sizeof(WgDesc) * L.wg.size(),
+    e = hipMemcpyAsync(c->ws + L.o_wg, c->plan.wg.data(), sizeof(WgDesc) * c->plan.wg.size(),
                        hipMemcpyHostToDevice, c->stream);
   std::vector<WinState> ws(L.win.size());
   std::vector<InstState> is(L.inst.size());
@@ -366,7 +403,7 @@ int rewl_init(const rewl_params* params, int32_t n, const int32_t* win_lo, const
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->ws + L.o_sm, sm.data(), sizeof(int64_t) * sm.size(),
                        hipMemcpyHostToDevice, c->stream);
-  if (e == hipSuccess) e = prepare_sweep_lds(L.lds_bytes);
+  if (e == hipSuccess) e = prepare_sweep_lds((size_t)lds_budget_bytes());
   if (e == hipSuccess) e = launch_init(c->P, c->stream);
   // host vectors above are pageable; make sure the copies finished
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -381,7 +418,32 @@ int rewl_init(const rewl_params* params, int32_t n, const int32_t* win_lo, const
 int rewl_run_sweeps(rewl_ctx* c, int64_t flips) {
   if (!c || flips < 0) return REWL_E_INVAL;
   if (flips == 0) return REWL_OK;
-  return hip_rc(launch_sweep(c->P, c->lo.n_wg_ising, flips, c->lo.lds_bytes, c->stream));
+  return hip_rc(launch_sweep(c->P, c->plan.class_count, flips, c->plan.lds_bytes, c->stream));
+}
+
+int rewl_set_launch(rewl_ctx* c, int32_t page_bins, int32_t walkers_per_group, int32_t* out) {
+  if (!c || page_bins < 0 || walkers_per_group < 0) return REWL_E_INVAL;
+  LaunchPlan pl;
+  int rc = plan_launch(c->lo, lds_budget_bytes(), page_bins, walkers_per_group, pl);
+  if (rc) return rc;
+  rc = sync(c);  // no sweep may still read the old table
+  if (rc) return rc;
+  c->plan = pl;
+  fill_ptrs(c);
+  if (c->graph) {
+    (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+  }
+  rc = hip_rc(hipMemcpyAsync(c->ws + c->lo.o_wg, c->plan.wg.data(),
+                             sizeof(WgDesc) * c->plan.wg.size(), hipMemcpyHostToDevice, c->stream));
+  if (!rc) rc = sync(c);
+  if (!rc && out) {
+    out[0] = c->plan.P;
+    out[1] = c->plan.G;
+    out[2] = (int32_t)c->plan.lds_bytes;
+    out[3] = (int32_t)c->plan.wg.size();
+  }
+  return rc;
 }
 
 int rewl_merge(rewl_ctx* c) {
@@ -624,10 +686,13 @@ int rewl_restore(rewl_ctx* c, const void* buf, size_t n) {
   const unsigned char* p = static_cast<const unsigned char*>(buf) + sizeof(hdr);
   const Layout& L = c->lo;
   if (memcmp(p + L.o_inst, L.inst.data(), sizeof(InstDesc) * L.inst.size()) != 0 ||
-      memcmp(p + L.o_win, L.win.data(), sizeof(WinDesc) * L.win.size()) != 0 ||
-      memcmp(p + L.o_wg, L.wg.data(), sizeof(WgDesc) * L.wg.size()) != 0)
+      memcmp(p + L.o_win, L.win.data(), sizeof(WinDesc) * L.win.size()) != 0)
     return REWL_E_FORMAT;
   int rc = hip_rc(hipMemcpyAsync(c->ws, p, L.total, hipMemcpyHostToDevice, c->stream));
+  // the launch plan belongs to this context, not to the blob
+  if (!rc)
+    rc = hip_rc(hipMemcpyAsync(c->ws + L.o_wg, c->plan.wg.data(), sizeof(WgDesc) * c->plan.wg.size(),
+                               hipMemcpyHostToDevice, c->stream));
   if (!rc) rc = sync(c);
   return rc;
 }

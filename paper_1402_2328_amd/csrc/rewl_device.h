@@ -26,6 +26,23 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
   return c;
 }
 
+// Rounds [FIRST, LAST) of Philox4x32-10; round r uses the key bumped r
+// times.  philox_rounds<0, 10> equals philox10.  Splitting lets a kernel
+// spread the 10 rounds over latency gaps of other work.
+template <int FIRST, int LAST>
+__device__ __forceinline__ uint4 philox_rounds(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = FIRST; r < LAST; ++r) {
+    const uint32_t kr0 = k0 + (uint32_t)r * 0x9E3779B9u;
+    const uint32_t kr1 = k1 + (uint32_t)r * 0xBB67AE85u;
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ kr0, (uint32_t)p1,
+                   (uint32_t)(p0 >> 32) ^ c.w ^ kr1, (uint32_t)p0);
+  }
+  return c;
+}
+
 // exp(x) for x in [-40, 0): x = n ln2 + r with n = rint(x / ln2) and r from a
 // two-part split of ln2 (Cody and Waite); exp(r) by its degree-13 Taylor
 // polynomial in Horner form with fused multiply-adds; result 2^n exp(r).
@@ -80,11 +97,28 @@ __device__ __forceinline__ bool accept64(uint64_t u, double delta) {
   return (double)u * 0x1p-53 < exp_det(delta);
 }
 
+// The same decision without branches: exp_det is evaluated for every lane
+// (its argument clamped into [-40, 0]) and used only where delta lies in
+// [-40, 0), so the outcome is bit-identical to accept64.
+__device__ __forceinline__ bool accept64_flat(uint64_t u, double delta) {
+  const double x = fmin(fmax(delta, -40.0), 0.0);
+  const double e = exp_det(x);
+  const bool mid = (double)u * 0x1p-53 < e;
+  return (delta >= 0.0) || (delta < -40.0 ? (u == 0) : mid);
+}
+
 // Same with a 24-bit uniform (exp(-17) < 2^-24).
 __device__ __forceinline__ bool accept32(uint32_t u, float delta) {
   if (delta >= 0.0f) return true;
   if (delta < -17.0f) return u == 0;
   return (float)u * 0x1p-24f < expf_det(delta);
+}
+
+__device__ __forceinline__ bool accept32_flat(uint32_t u, float delta) {
+  const float x = fminf(fmaxf(delta, -17.0f), 0.0f);
+  const float e = expf_det(x);
+  const bool mid = (float)u * 0x1p-24f < e;
+  return (delta >= 0.0f) || (delta < -17.0f ? (u == 0) : mid);
 }
 
 // ---- two-float arithmetic (Knuth's TwoSum, Dekker's FastTwoSum) ----

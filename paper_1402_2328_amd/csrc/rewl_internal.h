@@ -16,6 +16,7 @@ constexpr int kMaxWalkersPerWindow = 64;
 constexpr int kMaxL = 64;
 constexpr int kSweepWave = 64;    // one wavefront per sweep workgroup
 constexpr int kMaxTemps = 16384;  // rewl_thermo temperatures per call
+constexpr int kMinPageBins = 16;  // smallest ln g page the launch planner picks
 
 enum Model : int32_t { kIsing = 0, kPotts = 1 };
 enum Prec : int32_t { kFP64 = 0, kFP32C = 1 };
@@ -85,14 +86,16 @@ struct DevPtrs {
   int32_t n_inst, n_win, n_slots, n_wg;
   int32_t lds_stride;        // lanes per LDS row of the sweep kernel
   int32_t lds_nw;            // 32-bit lattice words per lane in LDS
-  int32_t lds_nb;            // ln g / H rows per lane in LDS
+  int32_t page_bins;         // ln g / H page rows per lane in LDS
   int32_t prec;
 };
 
 // Launchers (kernels TU).  All enqueue on `s` and return the launch status.
 hipError_t launch_init(const DevPtrs& P, hipStream_t s);
-hipError_t launch_sweep(const DevPtrs& P, int32_t n_wg_ising, int64_t flips, size_t lds_bytes,
-                        hipStream_t s);
+// class_count: workgroups of Ising L <= 32, Ising 32 < L <= 64, Potts (in
+// that order in the workgroup table).
+hipError_t launch_sweep(const DevPtrs& P, const int32_t* class_count, int64_t flips,
+                        size_t lds_bytes, hipStream_t s);
 hipError_t launch_merge(const DevPtrs& P, hipStream_t s);
 hipError_t launch_exchange(const DevPtrs& P, hipStream_t s);
 hipError_t launch_join(const DevPtrs& P, int32_t instance, int32_t normalise, hipStream_t s);

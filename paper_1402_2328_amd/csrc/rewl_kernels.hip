@@ -1,15 +1,7 @@
-// REWL kernels for gfx950 (MI355X).
+// REWL kernels for gfx950 (MI355X), everything except the sweep (which is
+// in rewl_sweep.hip).
 //
-// Hot path: k_sweep runs one Wang-Landau walker per lane (Sec. 2).  A
-// workgroup is a single 64-lane wavefront holding up to 64 walkers of one
-// instance; for the whole launch each walker's lattice (int8 spins), ln g
-// and H over its window live in LDS, interleaved column-wise so that lane l
-// owns 32-bit column l of every row (no two lanes share a word, reads of one
-// row by all lanes fall into distinct banks).  Random numbers come from
-// Philox4x32-10 in registers, keyed by (walker slot, attempt), so a walker's
-// trajectory does not depend on how walkers are mapped to lanes.
-//
-// Cold path, once per cycle: k_merge_windows (flatness by block reductions
+// Once per cycle: k_merge_windows (flatness by block reductions
 // and the in-window average), k_merge_finish, k_exchange (Eq. 1, swaps
 // configuration indices, never lattice data), k_exchange_finish.  End of
 // run: k_join (Sec. 3 joining + normalisation in FP64) and k_thermo
@@ -140,166 +132,6 @@ __global__ void k_init(DevPtrs P) {
   P.att[g] = 0;
   P.watt[g] = wa;
   if (dist_to(E, elo, ehi) != 0) atomicMin(&P.ist[I.inst].error, -7);
-}
-
-// ---------------------------------------------------------------------------
-// Sweep: `flips` Wang-Landau attempts per walker, one walker per lane.
-// ---------------------------------------------------------------------------
-template <int MODEL, int PREC>
-__global__ __launch_bounds__(kSweepWave) void k_sweep(DevPtrs P, int64_t flips, int32_t wg_offset) {
-  extern __shared__ __align__(16) unsigned char lds[];
-  const WgDesc wg = P.wg[wg_offset + blockIdx.x];
-  const InstDesc& Ig = P.inst[wg.inst];
-  if (P.ist[wg.inst].done || P.ist[wg.inst].error) return;
-  const int lane = threadIdx.x;
-  if (lane >= wg.count) return;
-
-  const int S = P.lds_stride;
-  const int NW = P.lds_nw;
-  const int NB = P.lds_nb;
-  uint32_t* sw = reinterpret_cast<uint32_t*>(lds);                  // [NW][S] spin words
-  unsigned char* sb = lds;                                           // byte view
-  double* lg = reinterpret_cast<double*>(lds + (size_t)4 * NW * S);  // [NB][S] (FP64)
-  float* lgh = reinterpret_cast<float*>(lg);                         // [NB][S] (FP32C hi)
-  float* lgl = lgh + (size_t)NB * S;                                 // [NB][S] (FP32C lo)
-  uint32_t* hl = reinterpret_cast<uint32_t*>(lds + (size_t)4 * NW * S + (size_t)8 * NB * S);
-
-  const int L = Ig.L, N = Ig.N, q = Ig.q, bshift = Ig.binw_shift;
-  const float invL = Ig.invL;
-  const uint32_t k0 = Ig.key0, k1 = Ig.key1;
-  const uint32_t tagw = kTagMC | ((uint32_t)Ig.inst << 8);
-
-  const int g = wg.slot_first + lane;
-  const int loc = g - Ig.slot_base;
-  const int w = loc / Ig.m;
-  const int k = loc - w * Ig.m;
-  const WinDesc W = P.win[Ig.win_base + w];
-  const WinState WS = P.wst[Ig.win_base + w];
-  const int lo = W.lo, hi = W.hi, nb = W.nb;
-  const bool frozen = WS.frozen != 0;
-  const double lnf = WS.lnf;
-  const float lnf32 = (float)WS.lnf;
-
-  // ---- stage in: lattice, ln g, H ----
-  const int cfg = P.cfg[g];
-  const uint32_t* src = reinterpret_cast<const uint32_t*>(
-      P.spins + Ig.spin_base + (int64_t)(cfg - Ig.slot_base) * Ig.npad);
-  const int nwi = (N + 3) >> 2;  // this instance's lattice words (<= NW)
-  for (int i = 0; i < nwi; ++i) sw[i * S + lane] = src[i];
-  const int64_t base = W.lng_base + (int64_t)k * nb;
-  for (int j = 0; j < nb; ++j) {
-    if (PREC == kFP64) {
-      lg[j * S + lane] = P.lng[base + j];
-    } else {
-      lgh[j * S + lane] = P.lhi[base + j];
-      lgl[j * S + lane] = P.llo[base + j];
-    }
-    hl[j * S + lane] = P.H[base + j];
-  }
-
-  int32_t E = P.E[g];
-  uint64_t att = P.att[g];
-  int bin = (E - Ig.emin) >> bshift;
-  if (bin < lo || bin > hi) {  // only reachable through corrupted state
-    atomicMin(&P.ist[wg.inst].error, -6);
-    return;
-  }
-  const int lane4 = lane * 4;
-  const int S4 = S * 4;
-  auto saddr = [&](int site) { return (site >> 2) * S4 + lane4 + (site & 3); };
-
-  double lcur = 0.0;
-  float hcur = 0.0f, lcur_lo = 0.0f;
-  if (PREC == kFP64) lcur = lg[(bin - lo) * S + lane];
-  else {
-    hcur = lgh[(bin - lo) * S + lane];
-    lcur_lo = lgl[(bin - lo) * S + lane];
-  }
-
-  for (int64_t t = 0; t < flips; ++t) {
-    const uint4 r = philox10(make_uint4((uint32_t)att, (uint32_t)(att >> 32), (uint32_t)loc, tagw),
-                             k0, k1);
-    ++att;
-    const int site = (int)__umulhi(r.x, (uint32_t)N);
-    const int y = (int)(((float)site + 0.5f) * invL);
-    const int x = site - y * L;
-    const int row = y * L;
-    const int xr = (x + 1 == L) ? 0 : x + 1;
-    const int xl = (x == 0) ? L - 1 : x - 1;
-    const int rd = (y + 1 == L) ? 0 : row + L;
-    const int ru = (y == 0) ? N - L : row - L;
-    const int s0 = (int)(int8_t)sb[saddr(site)];
-    const int a = (int)(int8_t)sb[saddr(row + xr)];
-    const int b = (int)(int8_t)sb[saddr(row + xl)];
-    const int c = (int)(int8_t)sb[saddr(rd + x)];
-    const int d = (int)(int8_t)sb[saddr(ru + x)];
-    int dE, nv, db;
-    if (MODEL == kIsing) {
-      nv = -s0;
-      dE = 2 * s0 * (a + b + c + d);
-      db = dE >> 2;
-    } else {
-      int v = s0 + 1 + (int)__umulhi(r.y, (uint32_t)(q - 1));
-      v = (v >= q) ? v - q : v;
-      nv = v;
-      dE = ((a == s0) + (b == s0) + (c == s0) + (d == s0)) -
-           ((a == v) + (b == v) + (c == v) + (d == v));
-      db = dE >> bshift;
-    }
-    const int bn = bin + db;
-    const bool inwin = (bn >= lo) && (bn <= hi);
-    const int jn = (inwin ? bn : bin) - lo;
-    bool acc;
-    if (PREC == kFP64) {
-      const double ln = lg[jn * S + lane];
-      acc = inwin && accept64(u53(r.z, r.w), lcur - ln);
-      if (acc) lcur = ln;
-    } else {
-      const float nh = lgh[jn * S + lane];
-      const float nl = lgl[jn * S + lane];
-      const float delta = (hcur - nh) + (lcur_lo - nl);
-      acc = inwin && accept32(r.z >> 8, delta);
-      if (acc) {
-        hcur = nh;
-        lcur_lo = nl;
-      }
-    }
-    if (acc) {
-      sb[saddr(site)] = (unsigned char)(int8_t)nv;
-      E += dE;
-      bin = bn;
-    }
-    if (!frozen) {
-      const int j = (bin - lo) * S + lane;
-      if (PREC == kFP64) {
-        lcur = lcur + lnf;
-        lg[j] = lcur;
-      } else {
-        df_add1(hcur, lcur_lo, lnf32, hcur, lcur_lo);
-        lgh[j] = hcur;
-        lgl[j] = lcur_lo;
-      }
-      hl[j] += 1u;
-    }
-  }
-
-  // ---- stage out ----
-  uint32_t* dst = reinterpret_cast<uint32_t*>(
-      P.spins + Ig.spin_base + (int64_t)(cfg - Ig.slot_base) * Ig.npad);
-  for (int i = 0; i < nwi; ++i) dst[i] = sw[i * S + lane];
-  if (!frozen) {
-    for (int j = 0; j < nb; ++j) {
-      if (PREC == kFP64) {
-        P.lng[base + j] = lg[j * S + lane];
-      } else {
-        P.lhi[base + j] = lgh[j * S + lane];
-        P.llo[base + j] = lgl[j * S + lane];
-      }
-      P.H[base + j] = hl[j * S + lane];
-    }
-  }
-  P.E[g] = E;
-  P.att[g] = att;
 }
 
 // ---------------------------------------------------------------------------
@@ -668,39 +500,6 @@ __global__ void k_thermo(DevPtrs P, int32_t instance, int32_t nT) {
 hipError_t launch_init(const DevPtrs& P, hipStream_t s) {
   const int bs = 64;
   hipLaunchKernelGGL(k_init, dim3((P.n_slots + bs - 1) / bs), dim3(bs), 0, s, P);
-  return hipGetLastError();
-}
-
-hipError_t prepare_sweep_lds(size_t lds_bytes) {
-  const void* fns[] = {(const void*)k_sweep<kIsing, kFP64>, (const void*)k_sweep<kPotts, kFP64>,
-                       (const void*)k_sweep<kIsing, kFP32C>, (const void*)k_sweep<kPotts, kFP32C>};
-  for (const void* f : fns) {
-    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
-}
-
-hipError_t launch_sweep(const DevPtrs& P, int32_t n_wg_ising, int64_t flips, size_t lds_bytes,
-                        hipStream_t s) {
-  // The workgroup table lists all Ising workgroups first, then the Potts
-  // ones; each model runs its own specialisation of the sweep.
-  const int n_potts = P.n_wg - n_wg_ising;
-  if (P.prec == kFP64) {
-    if (n_wg_ising > 0)
-      hipLaunchKernelGGL((k_sweep<kIsing, kFP64>), dim3(n_wg_ising), dim3(kSweepWave), lds_bytes, s,
-                         P, flips, 0);
-    if (n_potts > 0)
-      hipLaunchKernelGGL((k_sweep<kPotts, kFP64>), dim3(n_potts), dim3(kSweepWave), lds_bytes, s, P,
-                         flips, n_wg_ising);
-  } else {
-    if (n_wg_ising > 0)
-      hipLaunchKernelGGL((k_sweep<kIsing, kFP32C>), dim3(n_wg_ising), dim3(kSweepWave), lds_bytes, s,
-                         P, flips, 0);
-    if (n_potts > 0)
-      hipLaunchKernelGGL((k_sweep<kPotts, kFP32C>), dim3(n_potts), dim3(kSweepWave), lds_bytes, s, P,
-                         flips, n_wg_ising);
-  }
   return hipGetLastError();
 }
 

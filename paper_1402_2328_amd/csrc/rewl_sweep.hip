@@ -1,0 +1,421 @@
+// The REWL hot path on gfx950: Wang-Landau sweeps, one walker per lane.
+//
+// Each workgroup is one 64-lane wavefront holding up to 64 walkers of one
+// instance.  For the duration of a launch every walker keeps in LDS
+//   * its lattice: Ising spins as bit rows (one 32-bit word per row for
+//     L <= 32, two for L <= 64), Potts spins as bytes;
+//   * a page of P consecutive bins of its ln g and H window, kept as a ring.
+//     Walkers move at most D bins per attempt (D = 2 for Ising and q = 2
+//     Potts, 4 for q >= 3 Potts); the page always covers [bin - 2D,
+//     bin + 2D] inside the window and follows the walker by at most D bins
+//     per move through device memory, with the fetched bins committed one
+//     attempt later.  Windows of at most P bins live in LDS entirely.
+// LDS is interleaved by lane: element e of lane l sits at e * S + l (S =
+// lanes per workgroup), so the 32-bit words that one instruction touches
+// across the wavefront fall into consecutive banks.  Random numbers come
+// from Philox4x32-10 keyed by (walker slot, attempt), so results do not
+// depend on the walker-to-lane mapping, page size or launch shape.
+#include <math.h>
+
+#include "rewl_device.h"
+#include "rewl_internal.h"
+
+namespace rewl {
+
+// Pins a Philox block in registers at this point of the program: an empty
+// asm statement (no instruction) that takes the four words as in/out
+// operands, so the compiler can neither sink the rounds that produce them
+// below it nor merge slices across it.
+#define REWL_PIN4(v) asm volatile("" : "+v"((v).x), "+v"((v).y), "+v"((v).z), "+v"((v).w))
+
+template <int MODEL, int PREC, int ROWW>
+__global__ __launch_bounds__(kSweepWave) void k_sweep(DevPtrs P, int64_t flips, int32_t wg_offset) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const WgDesc wg = P.wg[wg_offset + blockIdx.x];
+  const InstDesc& Ig = P.inst[wg.inst];
+  if (P.ist[wg.inst].done || P.ist[wg.inst].error) return;
+  const int lane = threadIdx.x;
+  if (lane >= wg.count) return;
+
+  const int S = P.lds_stride;
+  const int NWL = P.lds_nw;   // lattice words per lane
+  const int PG = P.page_bins; // page rows per lane
+  uint32_t* lat = reinterpret_cast<uint32_t*>(lds);                           // [NWL][S]
+  unsigned char* latb = lds;                                                   // byte view (Potts)
+  unsigned char* pg = lds + (size_t)4 * NWL * S;
+  double* plg = reinterpret_cast<double*>(pg);                                 // [PG][S] FP64
+  float* plh = reinterpret_cast<float*>(pg);                                   // [PG][S] FP32C hi
+  float* pll = plh + (size_t)PG * S;                                           // [PG][S] FP32C lo
+  uint32_t* pH = reinterpret_cast<uint32_t*>(pg + (size_t)8 * PG * S);         // [PG][S]
+
+  const int L = Ig.L, N = Ig.N, q = Ig.q, bshift = Ig.binw_shift;
+  const float invL = Ig.invL;
+  const uint32_t k0 = Ig.key0, k1 = Ig.key1;
+  const uint32_t tagw = kTagMC | ((uint32_t)Ig.inst << 8);
+  const int D = (MODEL == kPotts && bshift == 0) ? 4 : 2;  // largest bin step of one move
+
+  const int g = wg.slot_first + lane;
+  const int loc = g - Ig.slot_base;
+  const int w = loc / Ig.m;
+  const int k = loc - w * Ig.m;
+  const WinDesc W = P.win[Ig.win_base + w];
+  const WinState WS = P.wst[Ig.win_base + w];
+  const int lo = W.lo, hi = W.hi, nb = W.nb;
+  const bool frozen = WS.frozen != 0;
+  const double lnf = WS.lnf;
+  const float lnf32 = (float)WS.lnf;
+  const int64_t gbase = W.lng_base + (int64_t)k * nb;  // global element of (walker, bin lo)
+  const int pn = nb < PG ? nb : PG;                     // page length of this walker
+
+  int32_t E = P.E[g];
+  uint64_t att = P.att[g];
+  int bin = (E - Ig.emin) >> bshift;
+  if (bin < lo || bin > hi) {  // only reachable through corrupted state
+    atomicMin(&P.ist[wg.inst].error, -6);
+    return;
+  }
+
+  // ---- stage in the lattice ----
+  const int cfg = P.cfg[g];
+  int8_t* gsp = P.spins + Ig.spin_base + (int64_t)(cfg - Ig.slot_base) * Ig.npad;
+  if (MODEL == kIsing) {
+    for (int y = 0; y < L; ++y) {
+      for (int part = 0; part < ROWW; ++part) {
+        uint32_t word = 0;
+        const int x0 = part * 32;
+        const int xe = (L - x0) < 32 ? (L - x0) : 32;
+        for (int b = 0; b < xe; ++b) word |= (uint32_t)(gsp[y * L + x0 + b] > 0) << b;
+        lat[(y * ROWW + part) * S + lane] = word;
+      }
+    }
+  } else {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(gsp);
+    const int nwi = (N + 3) >> 2;
+    for (int i = 0; i < nwi; ++i) lat[i * S + lane] = src[i];
+  }
+
+  // ---- page of ln g / H: a ring of pn slots over bins [pbase, pbase+pn) ----
+  // Slot of bin b: (ps + b - pbase) mod pn.  The page always covers
+  // [bin - 2D, bin + 2D] inside the window; after a move it shifts by at
+  // most D bins, writing the bins it drops back to device memory and
+  // fetching the bins it gains into registers, which are committed to LDS
+  // one attempt later (they cannot be reached before then), so the wave
+  // never waits for device memory inside the loop.
+  const int M = 2 * D;
+  int pbase = bin - (pn >> 1);
+  pbase = pbase < lo ? lo : pbase;
+  pbase = pbase > hi - pn + 1 ? hi - pn + 1 : pbase;
+  int ps = 0;
+  for (int j = 0; j < pn; ++j) {
+    const int64_t e = gbase + (pbase - lo) + j;
+    if (PREC == kFP64) {
+      plg[j * S + lane] = P.lng[e];
+    } else {
+      plh[j * S + lane] = P.lhi[e];
+      pll[j * S + lane] = P.llo[e];
+    }
+    pH[j * S + lane] = P.H[e];
+  }
+  auto slot_of = [&](int b) {
+    const int v = ps + (b - pbase);
+    return v >= pn ? v - pn : v;
+  };
+  constexpr int DMAX = (MODEL == kPotts) ? 4 : 2;
+  int pend_n = 0;
+  int pend_slot[DMAX];
+  double pend_l[DMAX];
+  float pend_hi[DMAX], pend_lo[DMAX];
+  uint32_t pend_H[DMAX];
+#pragma unroll
+  for (int i = 0; i < DMAX; ++i) {
+    pend_slot[i] = 0;
+    pend_l[i] = 0.0;
+    pend_hi[i] = pend_lo[i] = 0.0f;
+    pend_H[i] = 0;
+  }
+
+  double lcur = 0.0;
+  float hcur = 0.0f, lcur_lo = 0.0f;
+  if (PREC == kFP64) lcur = plg[(bin - pbase) * S + lane];
+  else {
+    hcur = plh[(bin - pbase) * S + lane];
+    lcur_lo = pll[(bin - pbase) * S + lane];
+  }
+
+  const int lane4 = lane * 4;
+  const int S4 = S * 4;
+  // addresses stay below 2^24, so 24-bit multiplies (full rate) suffice
+  auto pbyte = [&](int site) { return __mul24(site >> 2, S4) + lane4 + (site & 3); };
+  auto prow = [&](int row) { return __mul24(row, S) + lane; };
+
+  // Software pipeline: the Philox block of attempt t+1 (it depends only on
+  // the attempt counter) is computed in three slices placed in the latency
+  // shadows of attempt t -- after the lattice reads are issued, after the
+  // ln g read is issued, and beside the exponential.  sched_barrier keeps
+  // the compiler from hoisting the slices back together.
+  uint4 r = philox10(make_uint4((uint32_t)att, (uint32_t)(att >> 32), (uint32_t)loc, tagw), k0, k1);
+  for (int64_t t = 0; t < flips; ++t) {
+    const uint64_t an = att + 1;
+    const uint4 cn = make_uint4((uint32_t)an, (uint32_t)(an >> 32), (uint32_t)loc, tagw);
+    const int site = (int)__umulhi(r.x, (uint32_t)N);
+    const int y = (int)(((float)site + 0.5f) * invL);
+    const int x = site - __mul24(y, L);
+    const int xr = (x + 1 == L) ? 0 : x + 1;
+    const int xl = (x == 0) ? L - 1 : x - 1;
+    const int yd = (y + 1 == L) ? 0 : y + 1;
+    const int yu = (y == 0) ? L - 1 : y - 1;
+    int dE, db, nv = 0;
+    int widx = 0;
+    uint32_t wrow = 0;
+    uint4 rn;
+    if (MODEL == kIsing) {
+      // bit b of a row word: spin at x = 32 * part + b is +1
+      int s0, a, b, c, d;
+      if (ROWW == 1) {
+        widx = prow(y);
+        wrow = lat[widx];
+        const uint32_t wu = lat[prow(yu)];
+        const uint32_t wd = lat[prow(yd)];
+        __builtin_amdgcn_sched_barrier(0);
+        rn = philox_rounds<0, 4>(cn, k0, k1);
+        REWL_PIN4(rn);
+        __builtin_amdgcn_sched_barrier(0);
+        s0 = (wrow >> x) & 1;
+        a = (wrow >> xr) & 1;
+        b = (wrow >> xl) & 1;
+        c = (wd >> x) & 1;
+        d = (wu >> x) & 1;
+      } else {
+        const int px = x >> 5;
+        const uint32_t r0 = lat[prow(2 * y)];
+        const uint32_t r1 = lat[prow(2 * y + 1)];
+        const uint32_t wu = lat[prow(2 * yu + px)];
+        const uint32_t wd = lat[prow(2 * yd + px)];
+        __builtin_amdgcn_sched_barrier(0);
+        rn = philox_rounds<0, 4>(cn, k0, k1);
+        REWL_PIN4(rn);
+        __builtin_amdgcn_sched_barrier(0);
+        wrow = px ? r1 : r0;
+        s0 = (wrow >> (x & 31)) & 1;
+        a = (((xr >> 5) ? r1 : r0) >> (xr & 31)) & 1;
+        b = (((xl >> 5) ? r1 : r0) >> (xl & 31)) & 1;
+        c = (wd >> (x & 31)) & 1;
+        d = (wu >> (x & 31)) & 1;
+        widx = prow(2 * y + px);
+      }
+      // sigma = 2 bit - 1: dE = 2 s0 (sum of neighbours), bin step dE / 4
+      db = (2 * s0 - 1) * (a + b + c + d - 2);
+      dE = 4 * db;
+    } else {
+      const int rowy = __mul24(y, L);
+      const int s0 = (int)latb[pbyte(site)];
+      const int a = (int)latb[pbyte(rowy + xr)];
+      const int b = (int)latb[pbyte(rowy + xl)];
+      const int c = (int)latb[pbyte(__mul24(yd, L) + x)];
+      const int d = (int)latb[pbyte(__mul24(yu, L) + x)];
+      __builtin_amdgcn_sched_barrier(0);
+      rn = philox_rounds<0, 4>(cn, k0, k1);
+      REWL_PIN4(rn);
+      __builtin_amdgcn_sched_barrier(0);
+      int v = s0 + 1 + (int)__umulhi(r.y, (uint32_t)(q - 1));
+      v = (v >= q) ? v - q : v;
+      nv = v;
+      dE = ((a == s0) + (b == s0) + (c == s0) + (d == s0)) -
+           ((a == v) + (b == v) + (c == v) + (d == v));
+      db = dE >> bshift;
+    }
+    const int bn = bin + db;
+    const bool inwin = (bn >= lo) && (bn <= hi);
+    const int jn = prow(slot_of(inwin ? bn : bin));
+    bool acc;
+    if (PREC == kFP64) {
+      const double ln = plg[jn];
+      __builtin_amdgcn_sched_barrier(0);
+      rn = philox_rounds<4, 7>(rn, k0, k1);
+      REWL_PIN4(rn);
+      __builtin_amdgcn_sched_barrier(0);
+      const bool a = accept64_flat(u53(r.z, r.w), lcur - ln);
+      rn = philox_rounds<7, 10>(rn, k0, k1);
+      REWL_PIN4(rn);
+      acc = inwin && a;
+      lcur = acc ? ln : lcur;
+    } else {
+      const float nh = plh[jn];
+      const float nl = pll[jn];
+      __builtin_amdgcn_sched_barrier(0);
+      rn = philox_rounds<4, 7>(rn, k0, k1);
+      REWL_PIN4(rn);
+      __builtin_amdgcn_sched_barrier(0);
+      const bool a = accept32_flat(r.z >> 8, (hcur - nh) + (lcur_lo - nl));
+      rn = philox_rounds<7, 10>(rn, k0, k1);
+      REWL_PIN4(rn);
+      acc = inwin && a;
+      hcur = acc ? nh : hcur;
+      lcur_lo = acc ? nl : lcur_lo;
+    }
+    if (acc) {
+      if (MODEL == kIsing) {
+        lat[widx] = wrow ^ (1u << (x & 31));
+      } else {
+        latb[pbyte(site)] = (unsigned char)nv;
+      }
+      E += dE;
+      bin = bn;
+    }
+    if (!frozen) {
+      const int j = prow(slot_of(bin));
+      if (PREC == kFP64) {
+        lcur = lcur + lnf;
+        plg[j] = lcur;
+      } else {
+        df_add1(hcur, lcur_lo, lnf32, hcur, lcur_lo);
+        plh[j] = hcur;
+        pll[j] = lcur_lo;
+      }
+      atomicAdd(&pH[j], 1u);  // no-return LDS add: the lane owns this word
+    }
+    // commit the bins fetched one attempt ago, then follow the walker
+#pragma unroll
+    for (int i = 0; i < DMAX; ++i) {
+      if (i < pend_n) {
+        const int j = prow(pend_slot[i]);
+        if (PREC == kFP64) {
+          plg[j] = pend_l[i];
+        } else {
+          plh[j] = pend_hi[i];
+          pll[j] = pend_lo[i];
+        }
+        pH[j] = pend_H[i];
+      }
+    }
+    pend_n = 0;
+    if (pn < nb) {
+      const int top = pbase + pn - 1;
+      const int want_top = (bin + M < hi) ? bin + M : hi;
+      const int want_bot = (bin - M > lo) ? bin - M : lo;
+      const bool up = want_top > top;
+      const bool down = want_bot < pbase;
+      if (up || down) {
+        const int sh = up ? want_top - top : pbase - want_bot;  // 1..D
+#pragma unroll
+        for (int i = 0; i < DMAX; ++i) {
+          if (i < sh) {
+            // up: drop bin pbase+i, gain top+1+i; down: drop top-i, gain pbase-1-i
+            int es = up ? ps + i : ps + pn - 1 - i;
+            es = es >= pn ? es - pn : es;
+            const int drop = up ? pbase + i : top - i;
+            const int gain = up ? top + 1 + i : pbase - 1 - i;
+            const int j = prow(es);
+            if (!frozen) {
+              const int64_t eg = gbase + (drop - lo);
+              if (PREC == kFP64) {
+                P.lng[eg] = plg[j];
+              } else {
+                P.lhi[eg] = plh[j];
+                P.llo[eg] = pll[j];
+              }
+              P.H[eg] = pH[j];
+            }
+            const int64_t ng = gbase + (gain - lo);
+            if (PREC == kFP64) {
+              pend_l[i] = P.lng[ng];
+            } else {
+              pend_hi[i] = P.lhi[ng];
+              pend_lo[i] = P.llo[ng];
+            }
+            pend_H[i] = P.H[ng];
+            pend_slot[i] = es;
+          }
+        }
+        pend_n = sh;
+        if (up) {
+          pbase += sh;
+          ps += sh;
+          ps = ps >= pn ? ps - pn : ps;
+        } else {
+          pbase -= sh;
+          ps += pn - sh;
+          ps = ps >= pn ? ps - pn : ps;
+        }
+      }
+    }
+    r = rn;
+    ++att;
+  }
+
+  // ---- stage out ----
+#pragma unroll
+  for (int i = 0; i < DMAX; ++i) {
+    if (i < pend_n) {
+      const int j = prow(pend_slot[i]);
+      if (PREC == kFP64) {
+        plg[j] = pend_l[i];
+      } else {
+        plh[j] = pend_hi[i];
+        pll[j] = pend_lo[i];
+      }
+      pH[j] = pend_H[i];
+    }
+  }
+  if (!frozen) {
+    for (int j = 0; j < pn; ++j) {
+      const int64_t e = gbase + (pbase - lo) + j;
+      const int sl = prow(slot_of(pbase + j));
+      if (PREC == kFP64) {
+        P.lng[e] = plg[sl];
+      } else {
+        P.lhi[e] = plh[sl];
+        P.llo[e] = pll[sl];
+      }
+      P.H[e] = pH[sl];
+    }
+  }
+  if (MODEL == kIsing) {
+    for (int y = 0; y < L; ++y) {
+      for (int part = 0; part < ROWW; ++part) {
+        const uint32_t word = lat[(y * ROWW + part) * S + lane];
+        const int x0 = part * 32;
+        const int xe = (L - x0) < 32 ? (L - x0) : 32;
+        for (int b = 0; b < xe; ++b) gsp[y * L + x0 + b] = ((word >> b) & 1) ? 1 : -1;
+      }
+    }
+  } else {
+    uint32_t* dst = reinterpret_cast<uint32_t*>(gsp);
+    const int nwi = (N + 3) >> 2;
+    for (int i = 0; i < nwi; ++i) dst[i] = lat[i * S + lane];
+  }
+  P.E[g] = E;
+  P.att[g] = att;
+}
+
+hipError_t prepare_sweep_lds(size_t lds_bytes) {
+  const void* fns[] = {(const void*)k_sweep<kIsing, kFP64, 1>, (const void*)k_sweep<kIsing, kFP64, 2>,
+                       (const void*)k_sweep<kPotts, kFP64, 0>, (const void*)k_sweep<kIsing, kFP32C, 1>,
+                       (const void*)k_sweep<kIsing, kFP32C, 2>, (const void*)k_sweep<kPotts, kFP32C, 0>};
+  for (const void* f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Workgroups are grouped by kernel variant: [Ising L <= 32][Ising L <= 64][Potts].
+hipError_t launch_sweep(const DevPtrs& P, const int32_t* class_count, int64_t flips,
+                        size_t lds_bytes, hipStream_t s) {
+  const int n0 = class_count[0], n1 = class_count[1], n2 = class_count[2];
+  const dim3 blk(kSweepWave);
+  if (P.prec == kFP64) {
+    if (n0) hipLaunchKernelGGL((k_sweep<kIsing, kFP64, 1>), dim3(n0), blk, lds_bytes, s, P, flips, 0);
+    if (n1) hipLaunchKernelGGL((k_sweep<kIsing, kFP64, 2>), dim3(n1), blk, lds_bytes, s, P, flips, n0);
+    if (n2)
+      hipLaunchKernelGGL((k_sweep<kPotts, kFP64, 0>), dim3(n2), blk, lds_bytes, s, P, flips, n0 + n1);
+  } else {
+    if (n0) hipLaunchKernelGGL((k_sweep<kIsing, kFP32C, 1>), dim3(n0), blk, lds_bytes, s, P, flips, 0);
+    if (n1) hipLaunchKernelGGL((k_sweep<kIsing, kFP32C, 2>), dim3(n1), blk, lds_bytes, s, P, flips, n0);
+    if (n2)
+      hipLaunchKernelGGL((k_sweep<kPotts, kFP32C, 0>), dim3(n2), blk, lds_bytes, s, P, flips, n0 + n1);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace rewl

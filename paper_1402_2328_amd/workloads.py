@@ -29,6 +29,17 @@ CFG3 = config(POTTS, 20, q=10, n_windows=32, walkers_per_window=16, lnf_final=1e
 CFG4 = dict(CFG3, precision=FP32C)
 
 
+def bench_replicas(cfg, n_cu=256):
+    """Copies of `cfg` that fill every compute unit with resident sweep
+    workgroups once, for the default launch plan."""
+    from . import rewl
+    ctx = rewl.Context([rewl_params_of(cfg)])
+    plan = ctx.set_launch()
+    ctx.close()
+    per_cu = max(1, (160 * 1024) // plan["lds_bytes"])
+    return max(1, (n_cu * per_cu) // plan["workgroups"])
+
+
 def replicated(cfg, copies):
     """`copies` independent instances of one configuration.  They share the
     seed and differ by their instance index, which every random-number

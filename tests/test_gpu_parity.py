@@ -27,6 +27,8 @@ SMALL = {
                                            flips=1500, seed=12),
     "potts_q10_L8_h4_m4": WL.config(WL.POTTS, 8, q=10, n_windows=4, walkers_per_window=4,
                                     flips=1000, seed=4),
+    "ising_L40_h6_m2_tworow": WL.config(WL.ISING, 40, n_windows=6, walkers_per_window=2,
+                                        flips=3000, seed=8),
     "potts_q2_L8_h3_m2": WL.config(WL.POTTS, 8, q=2, n_windows=3, walkers_per_window=2,
                                    flips=700, seed=5),
     "potts_q3_L10_h6_m3": WL.config(WL.POTTS, 10, q=3, n_windows=6, walkers_per_window=3,
@@ -167,3 +169,44 @@ def test_unreachable_window_is_reported_on_both_sides():
     st = ctx.status(0)
     assert st["merges"] == 0 and st["rounds"] == 0 and st["attempts"] == 0
     assert ctx.running() == 0
+
+
+@pytest.mark.parametrize("name,page,group", [("ising_L16_h5_m4", 9, 0), ("ising_L16_h5_m4", 0, 5),
+                                             ("potts_q5_L12_h9_m7_ragged", 12, 13),
+                                             ("potts_q10_L8_h4_m4", 10, 3),
+                                             ("ising_L40_h6_m2_tworow", 17, 0),
+                                             ("potts_q10_L8_fp32c", 9, 7)])
+def test_page_size_and_group_shape_do_not_change_results(name, page, group):
+    """Small ln g pages force frequent re-centring through device memory."""
+    cfg = SMALL[name]
+    ctx = gpu_context([cfg])
+    plan = ctx.set_launch(page_bins=page, walkers_per_group=group)
+    print(f"[parity] {name}: plan {plan}", flush=True)
+    sim = oracle_sim(cfg)
+    F = cfg["flips_per_exchange"]
+    for seg in (3, 30):
+        ctx.run_cycles(seg, F)
+        for _ in range(seg):
+            oracle_cycle(sim, F)
+        compare_state(ctx, 0, sim)
+
+
+@pytest.mark.parametrize("cfg_name,replicas,sample", [("CFG2", 0, (0, 1, -1)),
+                                                      ("CFG3", 3, (0, 2)),
+                                                      ("CFG4", 2, (1,))])
+def test_full_size_configs_sampled(cfg_name, replicas, sample):
+    """Full-size workloads in the launch shape the benchmark uses; sampled
+    instances are checked walker by walker against the oracle."""
+    cfg = getattr(WL, cfg_name)
+    R = replicas or WL.bench_replicas(cfg)
+    ctx = gpu_context([cfg] * R)
+    F = cfg["flips_per_exchange"]
+    cycles = 2
+    ctx.run_cycles(cycles, F)
+    for i in sample:
+        i = i % R
+        print(f"[parity] {cfg_name} x{R}: instance {i}", flush=True)
+        sim = oracle_sim(cfg, instance=i)
+        for _ in range(cycles):
+            oracle_cycle(sim, F)
+        compare_state(ctx, i, sim)
