@@ -1,18 +1,27 @@
 """Throughput benchmark of the REWL hot path on one MI355X.
 
 A step is one REWL cycle over the whole batch: rewl_run_sweeps(F) (every
-walker does F Wang-Landau attempts), rewl_merge (flatness test and in-window
+walker makes F Wang-Landau attempts), rewl_merge (flatness test and in-window
 merge) and rewl_exchange (one replica-exchange round).  The workload is the
 2D Ising L=32 REWL configuration (16 windows x 8 walkers, 75 % overlap,
 flatness 0.8, exchange every 10^4 flips, FP64 ln g) replicated R times as
 independent instances so that the chip is filled; each copy carries its
-instance index in every random-number counter.
+instance index in every random-number counter.  The launch shape is chosen
+by rewl_autotune before timing (untimed; it restores the state it touched).
 
 Printed: one JSON line with spin-flip attempts/s, the sweep kernel's
-roofline position (timed with HIP events on the library's stream) and the
-single-threaded CPU oracle's attempts/s on a bounded sample.
+roofline position (kernel time from HIP events recorded on the library's
+stream) and the single-threaded CPU oracle's attempts/s on a bounded sample.
+
+--converge --config {cfg1,cfg2,cfg3,cfg34} runs R copies of a configuration
+to ln f <= ln f_final and reports time to convergence and accuracy: Ising
+against the exact density of states, Potts by the sum rule, exact
+low-energy counts and the C_V peak; cfg34 runs the q=10 Potts instances in
+FP64 and in two-float FP32 and compares them (progress lines precede the
+JSON line).
 """
 import argparse
+import hashlib
 import json
 import os
 import platform
@@ -24,19 +33,22 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X figures used for the roofline (see DESIGN.md, "Roofline").
+# MI355X figures used for the roofline (DESIGN.md, "Roofline").
 N_CU = 256
 CLOCK_HZ = 2.4e9
-VALU_LANE_OPS_PER_CLK_PER_CU = 64          # 4 SIMD x 16 lanes, full-rate 32-bit/FP64 ops
-PEAK_VALU = N_CU * VALU_LANE_OPS_PER_CLK_PER_CU * CLOCK_HZ   # 3.93e13 lane-ops/s
-# Algorithmic VALU work of one attempt, in full-rate lane-op slots:
-# Philox4x32-10 100, site/neighbour indexing 28, dE + window 8, WL test and
-# exp 32, update 8.
-VALU_SLOTS_PER_ATTEMPT = 176
-# Algorithmic LDS bytes of one attempt: 5 spin bytes read, 8 B ln g read,
-# 8 B ln g write, 4 B H read + 4 B H write, spin write (1 B x acceptance ~ 0.5)
-LDS_BYTES_PER_ATTEMPT = 29.5
+VALU_LANE_OPS_PER_CLK_PER_CU = 64          # 4 SIMD x 16 lanes, full-rate 32-bit / FP64 ops
+PEAK_VALU = N_CU * VALU_LANE_OPS_PER_CLK_PER_CU * CLOCK_HZ   # 3.93e13 lane-op/s
+# Algorithmic VALU work of one attempt in full-rate lane-op slots:
+# Philox4x32-10 120 (20 32x32->64 multiplies at 4 slots + 40 xors), site and
+# neighbour indexing 24, energy change and window test 8, acceptance with
+# the exponential 26, update 8.
+VALU_SLOTS_PER_ATTEMPT = 186
+# Algorithmic LDS bytes of one attempt (Ising L=32): three 4-byte lattice rows
+# read, 8 B ln g read, 8 B ln g written, 4 B histogram read-modify-write
+# (counted 8), 4 B lattice row written on acceptance (~0.5).
+LDS_BYTES_PER_ATTEMPT = 38.0
 PEAK_LDS = N_CU * 128 * CLOCK_HZ            # 128 B/clk/CU
+PROFILE = os.path.join(ROOT, "profiles", "k_sweep_ising_L32_pmc.json")
 
 
 def parse():
@@ -44,11 +56,18 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--replicas", type=int, default=0, help="instances of the L=32 config (0: fill chip)")
+    ap.add_argument("--replicas", type=int, default=1024, help="instances of the L=32 configuration")
     ap.add_argument("--flips", type=int, default=10000)
     ap.add_argument("--precision", choices=["fp64", "fp32c"], default="fp64")
+    ap.add_argument("--page-bins", type=int, default=0,
+                    help="fixed ln g page size for the sweep (0: autotune)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--converge", action="store_true")
+    ap.add_argument("--config", choices=["cfg1", "cfg2", "cfg3", "cfg34"], default="cfg2")
+    ap.add_argument("--max-minutes", type=float, default=50.0)
+    ap.add_argument("--copy-reference", action="store_true",
+                    help="only copy a 512 MiB device buffer 3 times (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -70,28 +89,157 @@ def cpu_baseline(flips, seconds):
     dt = time.perf_counter() - t0
     return {"value": cycles * W * flips / dt, "unit": "attempts/s", "cores": 1, "kind": "oracle",
             "sample": f"Ising L=32 REWL (16 windows x 8 walkers), {cycles} cycles of {flips} "
-                      f"attempts per walker from a fresh start, single thread, {dt:.1f} s",
-            "cpu": platform.processor() or platform.machine()}
+                      f"attempts per walker from a fresh start, one thread, {dt:.1f} s",
+            "cpu": platform.processor() or platform.machine(), "host_cpus": os.cpu_count()}
+
+
+def traffic_from_profile(R, flips, page):
+    """HBM bytes per sweep launch from the committed rocprofv3 counters, if
+    they were taken on the current kernel source and workload (else None)."""
+    try:
+        prof = json.load(open(PROFILE))
+    except (OSError, ValueError):
+        return None
+    src = open(os.path.join(ROOT, "paper_1402_2328_amd", "csrc", "rewl_sweep.hip"), "rb").read()
+    if prof.get("source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    if prof.get("replicas") != R or prof.get("flips") != flips or prof.get("page_bins") != page:
+        return None
+    return (prof["fetch_kib"] * prof["fetch_scale"] + prof["write_kib"] * prof["write_scale"]) * 1024
+
+
+def run_to_convergence(ctx, R, flips, max_s, tag):
+    """Cycles until every instance is finished (or max_s); returns the wall
+    time at which each instance finished."""
+    import torch
+    t0 = time.perf_counter()
+    cycles = 0
+    done_at = {}
+    while True:
+        ctx.run_cycles(100, flips, use_graph=True)
+        cycles += 100
+        torch.cuda.synchronize()
+        now = time.perf_counter() - t0
+        st = [ctx.status(i) for i in range(R)]
+        for i, s in enumerate(st):
+            if s["done"] and i not in done_at:
+                done_at[i] = now
+        if cycles % 1000 == 0 or len(done_at) == R:
+            stages = np.array([s["stage"].min() for s in st])
+            print(json.dumps({"run": tag, "cycles": cycles, "t": round(now, 1), "done": len(done_at),
+                              "stage_min": int(stages.min()),
+                              "stage_med": float(np.median(stages))}), flush=True)
+        if len(done_at) == R or now > max_s:
+            return done_at, cycles, now
+
+
+def cv_peak(ctx, i, T):
+    """Peak of C_V(T) per spin on the grid T, refined by a parabola."""
+    E, C = ctx.thermo(T, instance=i)
+    k = int(np.argmax(C))
+    k = min(max(k, 1), len(T) - 2)
+    y0, y1, y2 = C[k - 1], C[k], C[k + 1]
+    den = y0 - 2 * y1 + y2
+    off = 0.5 * (y0 - y2) / den if den != 0 else 0.0
+    h = T[1] - T[0]
+    return float(T[k] + off * h), float(y1 - 0.25 * (y0 - y2) * off)
+
+
+def converge(a):
+    """Runs R instances of a configuration to ln f <= lnf_final and reports
+    time to convergence and accuracy (Ising: against the exact DOS; Potts:
+    sum rule and exact low-energy counts, C_V peak; --config cfg34 also runs
+    the two-float FP32 form on the same instances and compares)."""
+    from oracle import exact_dos
+    from paper_1402_2328_amd import rewl
+    from paper_1402_2328_amd import workloads as WL
+    from tests.test_oracle_exact import load_ising_table
+    name = a.config
+    R = a.replicas
+    runs = {"cfg1": [("fp64", WL.CFG1)], "cfg2": [("fp64", WL.CFG2)], "cfg3": [("fp64", WL.CFG3)],
+            "cfg34": [("fp64", WL.CFG3), ("fp32c", WL.CFG4)]}[name]
+    out = {"metric": "time to ln f <= ln f_final and accuracy of ln g", "config": name,
+           "instances": R, "runs": {}}
+    lng_by_run = {}
+    for tag, cfg in runs:
+        ctx = rewl.Context([WL.rewl_params_of(cfg)] * R)
+        plan = ctx.autotune(cfg["flips_per_exchange"])
+        done_at, cycles, wall = run_to_convergence(ctx, R, cfg["flips_per_exchange"],
+                                                   a.max_minutes * 60 / len(runs), tag)
+        g = ctx.geometry[0]
+        N, nb = g["N"], g["nbins"]
+        res = {"precision": tag, "launch": plan, "converged": len(done_at), "cycles_run": cycles,
+               "wall_s_all": wall,
+               "wall_s_median": float(np.median(list(done_at.values()))) if done_at else None,
+               "cycles_to_converge": sorted(int(ctx.status(i)["done_merge"]) for i in done_at)}
+        lngs = {i: ctx.get_lng(i)[0] for i in sorted(done_at)}
+        lng_by_run[tag] = lngs
+        if cfg["model"] == WL.ISING and lngs:
+            exact = exact_dos.ln_g(load_ising_table(cfg["L"]))
+            fin = np.isfinite(exact)
+            errs = [float(np.max(np.abs(v[fin] - exact[fin]))) for v in lngs.values()]
+            res.update({"max_abs_err_vs_exact": errs, "median_max_abs_err": float(np.median(errs))})
+        elif lngs:
+            q = cfg["q"]
+            low = exact_dos.potts_low_energy(q, cfg["L"])
+            sums, lows, peaks = [], [], []
+            T = np.arange(0.60, 0.80, 1e-4)
+            for i, v in lngs.items():
+                fin = np.isfinite(v)
+                mx = np.max(v[fin])
+                sums.append(float(mx + np.log(np.sum(np.exp(v[fin] - mx))) - N * np.log(q)))
+                lows.append(max(abs(v[j] - np.log(c)) for j, c in low.items() if c))
+                Tp, Cp = cv_peak(ctx, i, T)
+                peaks.append((Tp, Cp / N))
+            res.update({"lse_minus_N_ln_q": sums, "max_abs_err_low_energy_counts": lows,
+                        "cv_peak_T_and_height_per_spin": peaks})
+        out["runs"][tag] = res
+        ctx.close()
+    if "fp32c" in lng_by_run and "fp64" in lng_by_run:
+        a64, a32 = lng_by_run["fp64"], lng_by_run["fp32c"]
+        common = sorted(set(a64) & set(a32))
+        d = []
+        for i in common:
+            fin = np.isfinite(a64[i]) & np.isfinite(a32[i])
+            d.append(float(np.max(np.abs(a64[i][fin] - a32[i][fin]))))
+        # the same statistic between independent FP64 instances sets the scale
+        ids = sorted(a64)
+        dd = []
+        for x, y in zip(ids[::2], ids[1::2]):
+            fin = np.isfinite(a64[x]) & np.isfinite(a64[y])
+            dd.append(float(np.max(np.abs(a64[x][fin] - a64[y][fin]))))
+        out["fp32c_vs_fp64_max_abs_diff"] = d
+        out["fp64_vs_fp64_independent_max_abs_diff"] = dd
+    return out
 
 
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); multi-GPU REWL is a design "
-              "note, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}): this build measures the "
+              "single-GPU hot path; multi-GPU REWL is a design note", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1402_2328_amd import rewl
     from paper_1402_2328_amd import workloads as WL
 
     torch.cuda.set_device(0)
+    if a.converge:
+        print(json.dumps(converge(a)), flush=True)
+        return
+    if a.copy_reference:
+        x = torch.empty(128 * 2 ** 20, dtype=torch.float32, device="cuda")
+        x.fill_(1.0)
+        for _ in range(3):
+            y = x.clone()
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_reference_bytes": 4 * x.numel(), "copies": 3, "check": float(y[0])}))
+        return
     prec = WL.FP64 if a.precision == "fp64" else WL.FP32C
     cfg = dict(WL.CFG2, precision=prec, flips_per_exchange=a.flips)
-    one = [WL.rewl_params_of(cfg)]
-    R = a.replicas if a.replicas > 0 else WL.bench_replicas(cfg)
-    params = one * R
-    ctx = rewl.Context(params)
-    plan = ctx.set_launch()
+    R = a.replicas
+    ctx = rewl.Context([WL.rewl_params_of(cfg)] * R)
+    plan = ctx.set_launch(page_bins=a.page_bins) if a.page_bins > 0 else ctx.autotune(a.flips)
     W = R * cfg["n_windows"] * cfg["walkers_per_window"]
     stream = ctx.stream
 
@@ -121,7 +269,7 @@ def main():
     achieved_valu = sweep_rate * VALU_SLOTS_PER_ATTEMPT
     st = ctx.status(0)
     out = {
-        "metric": "spin-flip attempts/s (REWL sweep+merge+exchange cycles)",
+        "metric": "spin-flip attempts/s (REWL sweep + merge + exchange cycles)",
         "value": value,
         "unit": "attempts/s",
         "n_gpus": 1,
@@ -138,8 +286,11 @@ def main():
                                f"instances", "replicas": R, "walkers": W, "flips": a.flips,
                    "precision": a.precision, "launch": plan},
         "roofline": {"bound": "alu", "achieved": achieved_valu / 1e12, "peak": PEAK_VALU / 1e12,
-                     "unit": "Tlane-op/s", "frac": achieved_valu / PEAK_VALU, "traffic": None,
+                     "unit": "Tlane-op/s", "frac": achieved_valu / PEAK_VALU,
+                     "traffic": traffic_from_profile(R, a.flips,
+                                                     plan.get("ising_L<=32", {}).get("page_bins")),
                      "kernel": "k_sweep", "kernel_ms": sweep_ms,
+                     "valu_slots_per_attempt": VALU_SLOTS_PER_ATTEMPT,
                      "lds_achieved_TBps": sweep_rate * LDS_BYTES_PER_ATTEMPT / 1e12,
                      "lds_frac": sweep_rate * LDS_BYTES_PER_ATTEMPT / PEAK_LDS},
         "sweep_attempts_per_s": sweep_rate,

@@ -109,15 +109,26 @@ int rewl_init(const rewl_params* params, int32_t n_instances,
  * ln g or H.  Errors: INVAL (flips < 0), HIP. */
 int rewl_run_sweeps(rewl_ctx* ctx, int64_t flips);
 
-/* Chooses the sweep's launch shape: page_bins ln g / H bins of each walker
- * kept in LDS (the rest of a larger window stays in device memory and the
- * page follows the walker) and walkers_per_group walkers per 64-lane
- * workgroup; 0 picks the default (the largest page that lets four
- * workgroups share a compute unit).  Results do not depend on the shape.
- * out: NULL or 4 entries {page_bins, walkers_per_group, LDS bytes per
+/* Launch shape of the sweep.  Walkers are grouped by kernel class:
+ * 0 = Ising L <= 32, 1 = Ising 32 < L <= 64, 2 = Potts.  For class cls (-1:
+ * all classes) keep page_bins ln g / H bins of each walker's window in LDS
+ * (the rest stays in device memory; the page follows the walker) and put
+ * walkers_per_group walkers in each 64-lane workgroup; 0 picks the default
+ * (the largest page that lets four workgroups share a compute unit).
+ * Results do not depend on the shape, only speed does.  out: NULL or 12
+ * entries, per class {page_bins, walkers_per_group, LDS bytes per
  * workgroup, workgroups}.  Synchronises.  Errors: INVAL (shape does not fit
  * in LDS), HIP. */
-int rewl_set_launch(rewl_ctx* ctx, int32_t page_bins, int32_t walkers_per_group, int32_t* out);
+int rewl_set_launch(rewl_ctx* ctx, int32_t cls, int32_t page_bins, int32_t walkers_per_group,
+                    int32_t* out);
+
+/* Measures `repeats` sweeps of `flips` attempts for each candidate page
+ * size (one per possible number of workgroups per compute unit) of every
+ * class and keeps the fastest.  The simulation state is saved to host
+ * memory first and restored afterwards, so tuning changes nothing but the
+ * launch shape.  out: as for rewl_set_launch.  Synchronises.
+ * Errors: INVAL, HIP. */
+int rewl_autotune(rewl_ctx* ctx, int64_t flips, int32_t repeats, int32_t* out);
 
 /* Enqueues the flatness test and in-window merge for every non-frozen window
  * (Sec. 2): when all m walkers of a window are flat at this check, their ln g

@@ -34,8 +34,13 @@ struct Layout {
   int32_t u_elems = 0;
   int32_t rep_elems = 0;
   int32_t r_elems = 0;
-  int32_t lat_words = 0;  // largest per-walker lattice in the sweep's LDS format, 32-bit words
-  int32_t nb_max = 0;     // largest window, bins
+  // per sweep class (Ising L <= 32, Ising L <= 64, Potts): largest lattice
+  // in the sweep's LDS format (32-bit words), largest window (bins), whether
+  // a q >= 3 Potts instance is present, walkers
+  int32_t lat_words[3] = {0, 0, 0};
+  int32_t nb_max[3] = {0, 0, 0};
+  int32_t potts3[3] = {0, 0, 0};
+  int32_t walkers[3] = {0, 0, 0};
   int32_t prec = 0;
   // byte offsets inside the workspace
   size_t o_inst, o_win, o_wg, o_ist, o_wst, o_sm, o_xs, o_cfg, o_E, o_att, o_watt, o_spins,
@@ -82,7 +87,6 @@ int build_layout(const rewl_params* params, int32_t n, const int32_t* wlo, const
   Lo.prec = params[0].precision;
   int32_t slot = 0, win = 0, woff = 0, rep = 0, rbase = 0;
   int64_t spin = 0, lng = 0;
-  int32_t nwmax = 0, nbmax = 0;
   for (int i = 0; i < n; ++i) {
     const rewl_params& p = params[i];
     int rc = check_params(p);
@@ -142,9 +146,13 @@ int build_layout(const rewl_params* params, int32_t n, const int32_t* wlo, const
     }
     // sweep LDS lattice: Ising bit rows (1 word per row for L <= 32, else 2),
     // Potts bytes
-    const int lw = I.model == REWL_ISING ? I.L * (I.L <= 32 ? 1 : 2) : (I.N + 3) / 4;
-    nwmax = std::max(nwmax, lw);
-    nbmax = std::max(nbmax, I.nbmax);
+    const int cls = I.model == REWL_POTTS ? 2 : (I.L <= 32 ? 0 : 1);
+    int lw = I.model == REWL_ISING ? I.L * (I.L <= 32 ? 1 : 2) : (I.N + 3) / 4;
+    lw += lw & 1;
+    Lo.lat_words[cls] = std::max(Lo.lat_words[cls], lw);
+    Lo.nb_max[cls] = std::max(Lo.nb_max[cls], I.nbmax);
+    Lo.potts3[cls] |= (I.model == REWL_POTTS && I.q >= 3);
+    Lo.walkers[cls] += I.W;
     slot += I.W;
     win += I.h;
     spin += (int64_t)I.W * I.npad;
@@ -156,8 +164,6 @@ int build_layout(const rewl_params* params, int32_t n, const int32_t* wlo, const
   Lo.lng_elems = lng;
   Lo.rep_elems = rep;
   Lo.r_elems = rbase;
-  Lo.lat_words = nwmax + (nwmax & 1);
-  Lo.nb_max = nbmax;
   // workspace offsets
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -196,58 +202,81 @@ int build_layout(const rewl_params* params, int32_t n, const int32_t* wlo, const
   return REWL_OK;
 }
 
-// Sweep launch plan: walkers per workgroup (G, one wavefront), ln g page
-// rows (P) and the workgroup table.  Per lane the sweep needs
-// 4 * lat_words + 12 * P bytes of LDS.  By default P is the largest page
-// that still lets T = 4 (else 3, 2, 1) full workgroups share a CU, as long
-// as that page holds min(nb_max, 32) bins.
-struct LaunchPlan {
-  int32_t G = 0, P = 0;
+// Sweep launch plan, per kernel class: walkers per workgroup (G, one
+// wavefront), ln g page rows (P), LDS bytes and the class's slice of the
+// workgroup table.  Per lane a class needs 4 * lat_words + 12 * P bytes of
+// LDS.  By default P is the largest page that still lets T = 4 (else 3, 2,
+// 1) full workgroups share a compute unit, as long as that page holds
+// min(nb_max, 32) bins.
+struct ClassPlan {
+  int32_t G = 0, P = 0, count = 0, offset = 0;
   size_t lds_bytes = 0;
+};
+struct LaunchPlan {
+  ClassPlan cls[3];
   std::vector<WgDesc> wg;
-  int32_t class_count[3] = {0, 0, 0};
 };
 
-int plan_launch(const Layout& Lo, int lds_budget, int page_req, int g_req, LaunchPlan& pl) {
-  pl = LaunchPlan();
-  const int lat = 4 * Lo.lat_words;
+int class_of(const InstDesc& I) { return I.model == REWL_POTTS ? 2 : (I.L <= 32 ? 0 : 1); }
+
+int plan_class(const Layout& Lo, int cls, int lds_budget, int page_req, int g_req, ClassPlan& cp) {
+  cp = ClassPlan();
+  if (Lo.walkers[cls] == 0) return REWL_OK;
+  const int lat = 4 * Lo.lat_words[cls];
+  const int nbm = Lo.nb_max[cls];
   int P = 0, G = kSweepWave;
   if (page_req > 0) {
-    P = std::min(page_req, Lo.nb_max);
+    P = std::min(page_req, nbm);
   } else {
-    const int want = std::min(Lo.nb_max, 32);
+    const int want = std::min(nbm, 32);
     for (int T = 4; T >= 1 && P == 0; --T) {
       const int p = (lds_budget / (kSweepWave * T) - lat) / 12;
-      if (p >= want) P = std::min(p, Lo.nb_max);
+      if (p >= want) P = std::min(p, nbm);
     }
     if (P == 0) P = want;
   }
   // the page ring must hold bin +- 2D (D = 4 for q >= 3 Potts, else 2)
-  bool potts3 = false;
-  for (const InstDesc& I : Lo.inst) potts3 |= (I.model == REWL_POTTS && I.q >= 3);
-  const int pmin = potts3 ? 17 : 9;
-  if (P < pmin && P < Lo.nb_max) P = std::min(pmin, Lo.nb_max);
+  const int pmin = Lo.potts3[cls] ? 17 : 9;
+  if (P < pmin && P < nbm) P = std::min(pmin, nbm);
   if (g_req > 0) G = std::min(g_req, kSweepWave);
   G = std::min(G, lds_budget / (lat + 12 * P));
   if (G < 1) return REWL_E_INVAL;
-  pl.G = G;
-  pl.P = P;
-  pl.lds_bytes = (size_t)G * (lat + 12 * P);
+  cp.G = G;
+  cp.P = P;
+  cp.lds_bytes = (size_t)G * (lat + 12 * P);
+  return REWL_OK;
+}
+
+// Builds the workgroup table: runs of up to G consecutive walkers of one
+// instance, class 0 first, then 1, then 2.
+void fill_table(const Layout& Lo, LaunchPlan& pl) {
+  pl.wg.clear();
   for (int cls = 0; cls < 3; ++cls) {
-    const size_t before = pl.wg.size();
-    for (const InstDesc& I : Lo.inst) {
-      const int c = I.model == REWL_POTTS ? 2 : (I.L <= 32 ? 0 : 1);
-      if (c != cls) continue;
-      for (int s0 = 0; s0 < I.W; s0 += G) {
-        WgDesc d{};
-        d.inst = I.inst;
-        d.slot_first = I.slot_base + s0;
-        d.count = std::min(G, I.W - s0);
-        pl.wg.push_back(d);
+    ClassPlan& cp = pl.cls[cls];
+    cp.offset = (int32_t)pl.wg.size();
+    if (cp.G > 0) {
+      for (const InstDesc& I : Lo.inst) {
+        if (class_of(I) != cls) continue;
+        for (int s0 = 0; s0 < I.W; s0 += cp.G) {
+          WgDesc d{};
+          d.inst = I.inst;
+          d.slot_first = I.slot_base + s0;
+          d.count = std::min(cp.G, I.W - s0);
+          pl.wg.push_back(d);
+        }
       }
     }
-    pl.class_count[cls] = (int32_t)(pl.wg.size() - before);
+    cp.count = (int32_t)pl.wg.size() - cp.offset;
   }
+}
+
+int plan_launch(const Layout& Lo, int lds_budget, int page_req, int g_req, LaunchPlan& pl) {
+  pl = LaunchPlan();
+  for (int cls = 0; cls < 3; ++cls) {
+    int rc = plan_class(Lo, cls, lds_budget, page_req, g_req, pl.cls[cls]);
+    if (rc) return rc;
+  }
+  fill_table(Lo, pl);
   return REWL_OK;
 }
 
@@ -302,9 +331,6 @@ void fill_ptrs(rewl_ctx* c) {
   P.n_win = (int32_t)L.win.size();
   P.n_slots = L.n_slots;
   P.n_wg = (int32_t)c->plan.wg.size();
-  P.lds_stride = c->plan.G;
-  P.lds_nw = L.lat_words;
-  P.page_bins = c->plan.P;
   P.prec = L.prec;
 }
 
@@ -320,8 +346,20 @@ int d2h(rewl_ctx* c, T* dst, const void* src, size_t count) {
   return sync(c);
 }
 
+hipError_t enqueue_sweeps(rewl_ctx* c, int64_t flips, int only_class = -1) {
+  for (int cls = 0; cls < 3; ++cls) {
+    if (only_class >= 0 && cls != only_class) continue;
+    const ClassPlan& cp = c->plan.cls[cls];
+    if (cp.count == 0) continue;
+    SweepShape sh{cp.G, c->lo.lat_words[cls], cp.P, cp.offset};
+    hipError_t e = launch_sweep_class(c->P, cls, sh, cp.count, flips, cp.lds_bytes, c->stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 int enqueue_cycle(rewl_ctx* c, int64_t flips) {
-  hipError_t e = launch_sweep(c->P, c->plan.class_count, flips, c->plan.lds_bytes, c->stream);
+  hipError_t e = enqueue_sweeps(c, flips);
   if (e == hipSuccess) e = launch_merge(c->P, c->stream);
   if (e == hipSuccess) e = launch_exchange(c->P, c->stream);
   return hip_rc(e);
@@ -418,15 +456,17 @@ int rewl_init(const rewl_params* params, int32_t n, const int32_t* win_lo, const
 int rewl_run_sweeps(rewl_ctx* c, int64_t flips) {
   if (!c || flips < 0) return REWL_E_INVAL;
   if (flips == 0) return REWL_OK;
-  return hip_rc(launch_sweep(c->P, c->plan.class_count, flips, c->plan.lds_bytes, c->stream));
+  return hip_rc(enqueue_sweeps(c, flips));
 }
 
-int rewl_set_launch(rewl_ctx* c, int32_t page_bins, int32_t walkers_per_group, int32_t* out) {
-  if (!c || page_bins < 0 || walkers_per_group < 0) return REWL_E_INVAL;
-  LaunchPlan pl;
-  int rc = plan_launch(c->lo, lds_budget_bytes(), page_bins, walkers_per_group, pl);
-  if (rc) return rc;
-  rc = sync(c);  // no sweep may still read the old table
+}  // extern "C"
+
+namespace {
+
+// Installs a plan: waits for queued sweeps (they read the old table),
+// uploads the workgroup table, drops a captured graph.
+int install_plan(rewl_ctx* c, const LaunchPlan& pl) {
+  int rc = sync(c);
   if (rc) return rc;
   c->plan = pl;
   fill_ptrs(c);
@@ -437,12 +477,94 @@ int rewl_set_launch(rewl_ctx* c, int32_t page_bins, int32_t walkers_per_group, i
   rc = hip_rc(hipMemcpyAsync(c->ws + c->lo.o_wg, c->plan.wg.data(),
                              sizeof(WgDesc) * c->plan.wg.size(), hipMemcpyHostToDevice, c->stream));
   if (!rc) rc = sync(c);
-  if (!rc && out) {
-    out[0] = c->plan.P;
-    out[1] = c->plan.G;
-    out[2] = (int32_t)c->plan.lds_bytes;
-    out[3] = (int32_t)c->plan.wg.size();
+  return rc;
+}
+
+void plan_out(const LaunchPlan& pl, int32_t* out) {
+  if (!out) return;
+  for (int cls = 0; cls < 3; ++cls) {
+    out[4 * cls + 0] = pl.cls[cls].P;
+    out[4 * cls + 1] = pl.cls[cls].G;
+    out[4 * cls + 2] = (int32_t)pl.cls[cls].lds_bytes;
+    out[4 * cls + 3] = pl.cls[cls].count;
   }
+}
+
+}  // namespace
+
+extern "C" {
+
+int rewl_set_launch(rewl_ctx* c, int32_t cls, int32_t page_bins, int32_t walkers_per_group,
+                    int32_t* out) {
+  if (!c || page_bins < 0 || walkers_per_group < 0 || cls < -1 || cls > 2) return REWL_E_INVAL;
+  LaunchPlan pl = c->plan;
+  for (int k = 0; k < 3; ++k) {
+    if (cls >= 0 && k != cls) continue;
+    int rc = plan_class(c->lo, k, lds_budget_bytes(), page_bins, walkers_per_group, pl.cls[k]);
+    if (rc) return rc;
+  }
+  fill_table(c->lo, pl);
+  int rc = install_plan(c, pl);
+  if (!rc) plan_out(c->plan, out);
+  return rc;
+}
+
+int rewl_autotune(rewl_ctx* c, int64_t flips, int32_t repeats, int32_t* out) {
+  if (!c || flips <= 0 || repeats < 1) return REWL_E_INVAL;
+  const Layout& L = c->lo;
+  const int budget = lds_budget_bytes();
+  // snapshot the state; every candidate starts from it and it is restored
+  // at the end, so tuning does not change the simulation
+  std::vector<unsigned char> snap(L.total);
+  int rc = d2h(c, snap.data(), c->ws, L.total);
+  if (rc) return rc;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return REWL_E_HIP;
+  LaunchPlan best = c->plan;
+  for (int cls = 0; cls < 3 && !rc; ++cls) {
+    if (L.walkers[cls] == 0) continue;
+    const int lat = 4 * L.lat_words[cls];
+    std::vector<int> cands;
+    for (int T = 1; T <= 12; ++T) {
+      int p = (budget / (kSweepWave * T) - lat) / 12;
+      p = std::min(p, L.nb_max[cls]);
+      if (p < (L.potts3[cls] ? 17 : 9) && p < L.nb_max[cls]) continue;
+      if (std::find(cands.begin(), cands.end(), p) == cands.end()) cands.push_back(p);
+    }
+    float best_ms = -1.0f;
+    for (int p : cands) {
+      LaunchPlan pl = best;
+      if (plan_class(L, cls, budget, p, 0, pl.cls[cls])) continue;
+      fill_table(L, pl);
+      rc = install_plan(c, pl);
+      if (!rc) rc = hip_rc(hipMemcpyAsync(c->ws, snap.data(), c->lo.o_wg, hipMemcpyHostToDevice, c->stream));
+      if (!rc) rc = hip_rc(hipMemcpyAsync(c->ws + L.o_ist, snap.data() + L.o_ist, L.total - L.o_ist,
+                                          hipMemcpyHostToDevice, c->stream));
+      if (!rc) rc = hip_rc(hipEventRecord(e0, c->stream));
+      for (int r = 0; r < repeats && !rc; ++r) rc = hip_rc(enqueue_sweeps(c, flips, cls));
+      if (!rc) rc = hip_rc(hipEventRecord(e1, c->stream));
+      if (!rc) rc = sync(c);
+      float ms = 0.0f;
+      if (!rc) rc = hip_rc(hipEventElapsedTime(&ms, e0, e1));
+      if (rc) break;
+      // every candidate runs the same walkers for the same attempts
+      const float per = ms;
+      if (best_ms < 0.0f || per < best_ms) {
+        best_ms = per;
+        best.cls[cls] = pl.cls[cls];
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  fill_table(L, best);
+  if (!rc) rc = install_plan(c, best);
+  // restore the state (everything except the workgroup table)
+  if (!rc) rc = hip_rc(hipMemcpyAsync(c->ws, snap.data(), L.o_wg, hipMemcpyHostToDevice, c->stream));
+  if (!rc) rc = hip_rc(hipMemcpyAsync(c->ws + L.o_ist, snap.data() + L.o_ist, L.total - L.o_ist,
+                                      hipMemcpyHostToDevice, c->stream));
+  if (!rc) rc = sync(c);
+  if (!rc) plan_out(c->plan, out);
   return rc;
 }
 

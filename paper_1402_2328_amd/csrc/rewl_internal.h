@@ -84,18 +84,23 @@ struct DevPtrs {
   double* thermo;            // [3][kMaxTemps]: T, <E>, C_V
   int32_t* joins;            // [windows] join bin of (w-1, w)
   int32_t n_inst, n_win, n_slots, n_wg;
-  int32_t lds_stride;        // lanes per LDS row of the sweep kernel
-  int32_t lds_nw;            // 32-bit lattice words per lane in LDS
-  int32_t page_bins;         // ln g / H page rows per lane in LDS
   int32_t prec;
+  int32_t pad;
+};
+
+// Launch shape of one sweep kernel class (Ising L <= 32, Ising L <= 64,
+// Potts): lanes per LDS row (walkers per workgroup), 32-bit lattice words
+// per lane, ln g / H page rows per lane, first workgroup in the table.
+struct SweepShape {
+  int32_t stride, nw, page, wg_offset;
 };
 
 // Launchers (kernels TU).  All enqueue on `s` and return the launch status.
 hipError_t launch_init(const DevPtrs& P, hipStream_t s);
-// class_count: workgroups of Ising L <= 32, Ising 32 < L <= 64, Potts (in
-// that order in the workgroup table).
-hipError_t launch_sweep(const DevPtrs& P, const int32_t* class_count, int64_t flips,
-                        size_t lds_bytes, hipStream_t s);
+// One sweep kernel class: 0 = Ising L <= 32, 1 = Ising 32 < L <= 64,
+// 2 = Potts; n_wg workgroups starting at sh.wg_offset of the table.
+hipError_t launch_sweep_class(const DevPtrs& P, int cls, SweepShape sh, int32_t n_wg, int64_t flips,
+                              size_t lds_bytes, hipStream_t s);
 hipError_t launch_merge(const DevPtrs& P, hipStream_t s);
 hipError_t launch_exchange(const DevPtrs& P, hipStream_t s);
 hipError_t launch_join(const DevPtrs& P, int32_t instance, int32_t normalise, hipStream_t s);

@@ -29,17 +29,17 @@ namespace rewl {
 #define REWL_PIN4(v) asm volatile("" : "+v"((v).x), "+v"((v).y), "+v"((v).z), "+v"((v).w))
 
 template <int MODEL, int PREC, int ROWW>
-__global__ __launch_bounds__(kSweepWave) void k_sweep(DevPtrs P, int64_t flips, int32_t wg_offset) {
+__global__ __launch_bounds__(kSweepWave) void k_sweep(DevPtrs P, SweepShape sh, int64_t flips) {
   extern __shared__ __align__(16) unsigned char lds[];
-  const WgDesc wg = P.wg[wg_offset + blockIdx.x];
+  const WgDesc wg = P.wg[sh.wg_offset + blockIdx.x];
   const InstDesc& Ig = P.inst[wg.inst];
   if (P.ist[wg.inst].done || P.ist[wg.inst].error) return;
   const int lane = threadIdx.x;
   if (lane >= wg.count) return;
 
-  const int S = P.lds_stride;
-  const int NWL = P.lds_nw;   // lattice words per lane
-  const int PG = P.page_bins; // page rows per lane
+  const int S = sh.stride;
+  const int NWL = sh.nw;   // lattice words per lane
+  const int PG = sh.page;  // page rows per lane
   uint32_t* lat = reinterpret_cast<uint32_t*>(lds);                           // [NWL][S]
   unsigned char* latb = lds;                                                   // byte view (Potts)
   unsigned char* pg = lds + (size_t)4 * NWL * S;
@@ -399,21 +399,18 @@ hipError_t prepare_sweep_lds(size_t lds_bytes) {
   return hipSuccess;
 }
 
-// Workgroups are grouped by kernel variant: [Ising L <= 32][Ising L <= 64][Potts].
-hipError_t launch_sweep(const DevPtrs& P, const int32_t* class_count, int64_t flips,
-                        size_t lds_bytes, hipStream_t s) {
-  const int n0 = class_count[0], n1 = class_count[1], n2 = class_count[2];
-  const dim3 blk(kSweepWave);
+hipError_t launch_sweep_class(const DevPtrs& P, int cls, SweepShape sh, int32_t n_wg, int64_t flips,
+                              size_t lds_bytes, hipStream_t s) {
+  if (n_wg <= 0) return hipSuccess;
+  const dim3 grid(n_wg), blk(kSweepWave);
   if (P.prec == kFP64) {
-    if (n0) hipLaunchKernelGGL((k_sweep<kIsing, kFP64, 1>), dim3(n0), blk, lds_bytes, s, P, flips, 0);
-    if (n1) hipLaunchKernelGGL((k_sweep<kIsing, kFP64, 2>), dim3(n1), blk, lds_bytes, s, P, flips, n0);
-    if (n2)
-      hipLaunchKernelGGL((k_sweep<kPotts, kFP64, 0>), dim3(n2), blk, lds_bytes, s, P, flips, n0 + n1);
+    if (cls == 0) hipLaunchKernelGGL((k_sweep<kIsing, kFP64, 1>), grid, blk, lds_bytes, s, P, sh, flips);
+    if (cls == 1) hipLaunchKernelGGL((k_sweep<kIsing, kFP64, 2>), grid, blk, lds_bytes, s, P, sh, flips);
+    if (cls == 2) hipLaunchKernelGGL((k_sweep<kPotts, kFP64, 0>), grid, blk, lds_bytes, s, P, sh, flips);
   } else {
-    if (n0) hipLaunchKernelGGL((k_sweep<kIsing, kFP32C, 1>), dim3(n0), blk, lds_bytes, s, P, flips, 0);
-    if (n1) hipLaunchKernelGGL((k_sweep<kIsing, kFP32C, 2>), dim3(n1), blk, lds_bytes, s, P, flips, n0);
-    if (n2)
-      hipLaunchKernelGGL((k_sweep<kPotts, kFP32C, 0>), dim3(n2), blk, lds_bytes, s, P, flips, n0 + n1);
+    if (cls == 0) hipLaunchKernelGGL((k_sweep<kIsing, kFP32C, 1>), grid, blk, lds_bytes, s, P, sh, flips);
+    if (cls == 1) hipLaunchKernelGGL((k_sweep<kIsing, kFP32C, 2>), grid, blk, lds_bytes, s, P, sh, flips);
+    if (cls == 2) hipLaunchKernelGGL((k_sweep<kPotts, kFP32C, 0>), grid, blk, lds_bytes, s, P, sh, flips);
   }
   return hipGetLastError();
 }

@@ -45,7 +45,8 @@ class rewl_instance_status(C.Structure):
 
 _lib = None
 
-EXPORTS = ["rewl_workspace_bytes", "rewl_init", "rewl_run_sweeps", "rewl_set_launch", "rewl_merge",
+EXPORTS = ["rewl_workspace_bytes", "rewl_init", "rewl_run_sweeps", "rewl_set_launch",
+           "rewl_autotune", "rewl_merge",
            "rewl_exchange", "rewl_run_cycles", "rewl_status", "rewl_running",
            "rewl_get_lng", "rewl_get_geometry", "rewl_get_walker", "rewl_get_walker_f32",
            "rewl_get_visited", "rewl_get_exchange_stats", "rewl_thermo", "rewl_checkpoint",
@@ -65,7 +66,8 @@ def lib():
     L.rewl_workspace_bytes.argtypes = [P, I32, P, P]
     L.rewl_init.argtypes = [P, I32, P, P, P, SZ, P, C.POINTER(C.c_void_p)]
     L.rewl_run_sweeps.argtypes = [P, I64]
-    L.rewl_set_launch.argtypes = [P, I32, I32, P]
+    L.rewl_set_launch.argtypes = [P, I32, I32, I32, P]
+    L.rewl_autotune.argtypes = [P, I64, I32, P]
     L.rewl_merge.argtypes = [P]
     L.rewl_exchange.argtypes = [P]
     L.rewl_run_cycles.argtypes = [P, I64, I64, I32]
@@ -158,12 +160,27 @@ class Context:
     def run_sweeps(self, flips):
         _check(lib().rewl_run_sweeps(self._h, int(flips)), "rewl_run_sweeps")
 
-    def set_launch(self, page_bins=0, walkers_per_group=0):
-        out = np.zeros(4, np.int32)
-        _check(lib().rewl_set_launch(self._h, int(page_bins), int(walkers_per_group), _p(out)),
-               "rewl_set_launch")
-        return {"page_bins": int(out[0]), "walkers_per_group": int(out[1]),
-                "lds_bytes": int(out[2]), "workgroups": int(out[3])}
+    CLASSES = ("ising_L<=32", "ising_L<=64", "potts")
+
+    @staticmethod
+    def _plan(out):
+        plan = {}
+        for c, name in enumerate(Context.CLASSES):
+            if out[4 * c + 3] > 0:
+                plan[name] = {"page_bins": int(out[4 * c]), "walkers_per_group": int(out[4 * c + 1]),
+                              "lds_bytes": int(out[4 * c + 2]), "workgroups": int(out[4 * c + 3])}
+        return plan
+
+    def set_launch(self, page_bins=0, walkers_per_group=0, cls=-1):
+        out = np.zeros(12, np.int32)
+        _check(lib().rewl_set_launch(self._h, int(cls), int(page_bins), int(walkers_per_group),
+                                     _p(out)), "rewl_set_launch")
+        return self._plan(out)
+
+    def autotune(self, flips, repeats=1):
+        out = np.zeros(12, np.int32)
+        _check(lib().rewl_autotune(self._h, int(flips), int(repeats), _p(out)), "rewl_autotune")
+        return self._plan(out)
 
     def merge(self):
         _check(lib().rewl_merge(self._h), "rewl_merge")

@@ -210,3 +210,34 @@ def test_full_size_configs_sampled(cfg_name, replicas, sample):
         for _ in range(cycles):
             oracle_cycle(sim, F)
         compare_state(ctx, i, sim)
+
+
+def test_autotune_changes_nothing_but_speed():
+    cfg = SMALL["potts_q5_L12_h9_m7_ragged"]
+    ctx = gpu_context([cfg, SMALL["ising_L16_h5_m4"], SMALL["ising_L40_h6_m2_tworow"]])
+    ctx.run_cycles(4, 1500)
+    plan = ctx.autotune(1500, repeats=1)
+    print(f"[parity] autotune plan {plan}", flush=True)
+    ctx.run_cycles(6, 1500)
+    sims = [oracle_sim(c, instance=i) for i, c in
+            enumerate([cfg, SMALL["ising_L16_h5_m4"], SMALL["ising_L40_h6_m2_tworow"]])]
+    for i, sim in enumerate(sims):
+        for _ in range(10):
+            oracle_cycle(sim, 1500)
+        compare_state(ctx, i, sim)
+
+
+def test_batched_mix_sampled():
+    """The uneven 64-instance batch (Ising L up to 64, Potts q = 2..10) in one
+    context; sampled instances of every kernel class checked in full."""
+    mix = WL.batched_mix()
+    ctx = gpu_context(mix)
+    F = 10000
+    cycles = 2
+    ctx.run_cycles(cycles, F, use_graph=True)
+    for i in (0, 4, 6, 13, 63):
+        print(f"[parity] batched mix instance {i}: {mix[i]['model']} L={mix[i]['L']}", flush=True)
+        sim = oracle_sim(mix[i], instance=i)
+        for _ in range(cycles):
+            oracle_cycle(sim, F)
+        compare_state(ctx, i, sim)
