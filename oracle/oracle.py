@@ -14,6 +14,7 @@ from . import build as _build
 
 ISING, POTTS = 0, 1
 FP64, FP32C = 0, 1
+HALVING, ONE_OVER_T = 0, 1
 
 
 class Params(C.Structure):
@@ -24,6 +25,7 @@ class Params(C.Structure):
         ("lnf_init", C.c_double), ("lnf_final", C.c_double),
         ("flips_per_exchange", C.c_int64), ("seed", C.c_uint64),
         ("precision", C.c_int32), ("instance", C.c_int32),
+        ("schedule", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -66,6 +68,9 @@ def lib():
         L.orc_get_exchange_stats.argtypes = [P, P, P, P]
         L.orc_join.argtypes = [P, P, P]
         L.orc_join_raw.argtypes = [P, P, P]
+        L.orc_jackknife.argtypes = [P, P, P]
+        L.orc_get_phase.argtypes = [P, C.c_int32]
+        L.orc_get_piece.argtypes = [P, C.c_int32, P]
         L.orc_philox4x32_10.argtypes = [P, P, P]
         L.orc_exp_spec.restype = C.c_double
         L.orc_exp_spec.argtypes = [C.c_double]
@@ -94,10 +99,10 @@ def _p(a):
 
 def make_params(model, L, q=2, n_windows=1, overlap=(3, 4), walkers_per_window=1,
                 flat=(4, 5), lnf_init=1.0, lnf_final=1e-8, flips_per_exchange=10000,
-                seed=1, precision=FP64, instance=0):
+                seed=1, precision=FP64, instance=0, schedule=HALVING):
     return Params(model, L, q, n_windows, overlap[0], overlap[1], walkers_per_window,
                   flat[0], flat[1], lnf_init, lnf_final, flips_per_exchange, seed,
-                  precision, instance)
+                  precision, instance, schedule, 0)
 
 
 class Sim:
@@ -182,7 +187,14 @@ class Sim:
         lib().orc_get_window(self._h, w, C.byref(lnf), C.byref(stage), C.byref(frozen),
                              _p(U), _p(sm))
         return {"lnf": lnf.value, "stage": stage.value, "frozen": frozen.value, "U": U,
-                "stage_merge": sm}
+                "stage_merge": sm, "phase": lib().orc_get_phase(self._h, w)}
+
+    def piece(self, slot):
+        w = slot // self.info.m
+        out = np.zeros(int(self.hi[w] - self.lo[w] + 1), np.float64)
+        if lib().orc_get_piece(self._h, slot, _p(out)):
+            raise ValueError("bad slot")
+        return out
 
     def exchange_stats(self):
         t = np.zeros(self.info.h, np.uint64)
@@ -190,6 +202,13 @@ class Sim:
         a = np.zeros(self.info.h, np.uint64)
         lib().orc_get_exchange_stats(self._h, _p(t), _p(r), _p(a))
         return t, r, a
+
+    def jackknife(self):
+        mean = np.zeros(self.info.nbins, np.float64)
+        err = np.zeros(self.info.nbins, np.float64)
+        if lib().orc_jackknife(self._h, _p(mean), _p(err)):
+            raise RuntimeError("jackknife needs a finished run with m >= 2")
+        return mean, err
 
     def join(self, normalise=True):
         out = np.zeros(self.info.nbins, np.float64)

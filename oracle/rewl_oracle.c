@@ -208,7 +208,8 @@ struct orc_sim {
   uint32_t** H;
   uint8_t** U;         /* per window */
   double* lnf;
-  int32_t *stage, *frozen;
+  int32_t *stage, *frozen, *phase;
+  double** pieces;     /* per slot: ln g captured before the freezing merge */
   int64_t* stage_merge;  /* [h][MAX_STAGES] */
   uint64_t *ex_try, *ex_acc, *ex_inr;
   int64_t merges;
@@ -318,6 +319,7 @@ orc_sim* orc_new(const orc_params* p, const int32_t* win_lo, const int32_t* win_
   if (p->flat_den <= 0 || p->flat_num < 0 || p->flat_num > p->flat_den) return NULL;
   if (p->flips_per_exchange < 0) return NULL;
   if (p->precision != ORC_FP64 && p->precision != ORC_FP32C) return NULL;
+  if (p->schedule != ORC_HALVING && p->schedule != ORC_ONE_OVER_T) return NULL;
   if (!(p->lnf_init > 0.0) || !(p->lnf_final > 0.0)) return NULL;
   if ((win_lo == NULL) != (win_hi == NULL)) return NULL;
 
@@ -381,6 +383,9 @@ orc_sim* orc_new(const orc_params* p, const int32_t* win_lo, const int32_t* win_
   s->lnf = (double*)xcalloc(s->h, 8);
   s->stage = (int32_t*)xcalloc(s->h, 4);
   s->frozen = (int32_t*)xcalloc(s->h, 4);
+  s->phase = (int32_t*)xcalloc(s->h, 4);
+  s->pieces = (double**)xcalloc(s->W, sizeof(double*));
+  for (int slot = 0; slot < s->W; ++slot) s->pieces[slot] = (double*)xcalloc(s->nb[slot / s->m], 8);
   s->stage_merge = (int64_t*)xcalloc((size_t)s->h * MAX_STAGES, 8);
   s->ex_try = (uint64_t*)xcalloc(s->h, 8);
   s->ex_acc = (uint64_t*)xcalloc(s->h, 8);
@@ -418,6 +423,8 @@ void orc_free(orc_sim* s) {
     if (s->lhi) { free(s->lhi[slot]); free(s->llo[slot]); }
   }
   for (int w = 0; s->U && w < s->h; ++w) free(s->U[w]);
+  for (int slot = 0; s->pieces && slot < s->W; ++slot) free(s->pieces[slot]);
+  free(s->pieces); free(s->phase);
   free(s->spins); free(s->cfg_id); free(s->E); free(s->att); free(s->watt);
   free(s->H); free(s->lng); free(s->lhi); free(s->llo); free(s->U);
   free(s->lnf); free(s->stage); free(s->frozen); free(s->stage_merge);
@@ -513,9 +520,39 @@ static void tree_sum32(float* vh, float* vl, int n, float* rh, float* rl) {
   *rh = vh[0]; *rl = vl[0];
 }
 
-/* Flatness check for every non-frozen window; when all m walkers of a
- * window are flat at the same check, average their ln g (geometric mean of
- * g), redistribute, reset H, ln f -> ln f / 2 (f -> sqrt f). */
+static double lng_at(const orc_sim* s, int slot, int j);
+
+/* Average the m walkers' ln g of window w bin by bin (geometric mean of g),
+ * redistribute, reset H. */
+static void merge_window(orc_sim* s, int w, double* t64, float* th, float* tl) {
+  int m = s->m;
+  for (int j = 0; j < s->nb[w]; ++j) {
+    if (s->lng) {
+      for (int k = 0; k < m; ++k) t64[k] = s->lng[w * m + k][j];
+      double mean = tree_sum64(t64, m) / (double)m;
+      for (int k = 0; k < m; ++k) s->lng[w * m + k][j] = mean;
+    } else {
+      for (int k = 0; k < m; ++k) { th[k] = s->lhi[w * m + k][j]; tl[k] = s->llo[w * m + k][j]; }
+      float sh, sl, mh, ml;
+      tree_sum32(th, tl, m, &sh, &sl);
+      orc_df_div_int(sh, sl, m, &mh, &ml);
+      for (int k = 0; k < m; ++k) { s->lhi[w * m + k][j] = mh; s->llo[w * m + k][j] = ml; }
+    }
+    for (int k = 0; k < m; ++k) s->H[w * m + k][j] = 0;
+  }
+}
+
+/* Flatness check for every non-frozen window (Sec. 2).
+ * Halving schedule: when all m walkers of a window are flat at the same
+ * check, their ln g are averaged and redistributed, H is reset and
+ * ln f -> ln f / 2 (f -> sqrt f).
+ * 1/t schedule (Belardinelli-Pereyra, which Sec. 2 names as compatible):
+ * phase A halves ln f, with the same merge, once every walker has visited
+ * every bin of the window's visited union; when ln f <= 1/t (t = attempts
+ * per walker / visited bins) the window enters phase B, where every check
+ * sets ln f = 1/t and merges.
+ * A window freezes when ln f <= ln f_final; the walkers' ln g just before
+ * that merge are kept for the jackknife. */
 int orc_merge(orc_sim* s) {
   if (!s) return -1;
   if (s->done) return 0;
@@ -532,34 +569,37 @@ int orc_merge(orc_sim* s) {
     uint64_t cnt = 0;
     for (int j = 0; j < nbw; ++j) cnt += s->U[w][j];
     int ready = cnt > 0;
-    for (int k = 0; k < m && ready; ++k) {
+    int phase_b = s->p.schedule == ORC_ONE_OVER_T && s->phase[w] == 1;
+    for (int k = 0; k < m && ready && !phase_b; ++k) {
       const uint32_t* H = s->H[w * m + k];
       uint64_t mn = UINT64_MAX, sum = 0;
       for (int j = 0; j < nbw; ++j) {
         sum += H[j];
         if (s->U[w][j] && H[j] < mn) mn = H[j];
       }
-      if ((uint64_t)s->p.flat_den * cnt * mn < (uint64_t)s->p.flat_num * sum) ready = 0;
+      if (s->p.schedule == ORC_HALVING) {
+        if ((uint64_t)s->p.flat_den * cnt * mn < (uint64_t)s->p.flat_num * sum) ready = 0;
+      } else if (mn == 0) {
+        ready = 0;
+      }
     }
     if (!ready) continue;
-    for (int j = 0; j < nbw; ++j) {
-      if (s->lng) {
-        for (int k = 0; k < m; ++k) t64[k] = s->lng[w * m + k][j];
-        double mean = tree_sum64(t64, m) / (double)m;
-        for (int k = 0; k < m; ++k) s->lng[w * m + k][j] = mean;
-      } else {
-        for (int k = 0; k < m; ++k) { th[k] = s->lhi[w * m + k][j]; tl[k] = s->llo[w * m + k][j]; }
-        float sh, sl, mh, ml;
-        tree_sum32(th, tl, m, &sh, &sl);
-        orc_df_div_int(sh, sl, m, &mh, &ml);
-        for (int k = 0; k < m; ++k) { s->lhi[w * m + k][j] = mh; s->llo[w * m + k][j] = ml; }
-      }
-      for (int k = 0; k < m; ++k) s->H[w * m + k][j] = 0;
+    /* new ln f and phase of this window */
+    double tinv = (double)cnt / (double)s->att[w * m];
+    double next = phase_b ? tinv : 0.5 * s->lnf[w];
+    int to_b = s->p.schedule == ORC_ONE_OVER_T && !phase_b && next <= tinv;
+    if (to_b) next = tinv;
+    if (next <= s->p.lnf_final)
+      for (int k = 0; k < m; ++k)
+        for (int j = 0; j < nbw; ++j) s->pieces[w * m + k][j] = lng_at(s, w * m + k, j);
+    merge_window(s, w, t64, th, tl);
+    if (!phase_b) {
+      if (s->stage[w] < MAX_STAGES) s->stage_merge[(size_t)w * MAX_STAGES + s->stage[w]] = s->merges;
+      s->stage[w] += 1;
     }
-    if (s->stage[w] < MAX_STAGES) s->stage_merge[(size_t)w * MAX_STAGES + s->stage[w]] = s->merges;
-    s->stage[w] += 1;
-    s->lnf[w] *= 0.5;
-    if (s->lnf[w] <= s->p.lnf_final) s->frozen[w] = 1;
+    s->lnf[w] = next;
+    if (to_b) s->phase[w] = 1;
+    if (next <= s->p.lnf_final) s->frozen[w] = 1;
   }
   free(t64); free(th); free(tl);
   int all = 1;
@@ -679,6 +719,17 @@ int orc_get_walker_f32(const orc_sim* s, int32_t slot, float* hi, float* lo) {
   return 0;
 }
 
+int orc_get_phase(const orc_sim* s, int32_t w) {
+  if (!s || w < 0 || w >= s->h) return -1;
+  return s->phase[w];
+}
+
+int orc_get_piece(const orc_sim* s, int32_t slot, double* out) {
+  if (!s || !out || slot < 0 || slot >= s->W) return -1;
+  memcpy(out, s->pieces[slot], sizeof(double) * (size_t)s->nb[slot / s->m]);
+  return 0;
+}
+
 int orc_get_window(const orc_sim* s, int32_t w, double* lnf, int32_t* stage, int32_t* frozen,
                    uint8_t* U, int64_t* stage_merge) {
   if (!s || w < 0 || w >= s->h) return -1;
@@ -790,6 +841,48 @@ int orc_join_raw(const orc_sim* s, double* out, int32_t* joins) {
                       (const uint8_t* const*)s->U, s->nbins, out, joins);
   for (int w = 0; w < s->h; ++w) free(reps[w]);
   free(reps);
+  return rc;
+}
+
+int orc_jackknife(const orc_sim* s, double* mean, double* err) {
+  if (!s || !mean || !err || s->m < 2 || !s->done) return -1;
+  int m = s->m;
+  double** reps = (double**)xcalloc(s->h, sizeof(double*));
+  for (int w = 0; w < s->h; ++w) reps[w] = (double*)xcalloc(s->nb[w], 8);
+  double* Rk = (double*)xcalloc((size_t)m * s->nbins, 8);
+  double* t = (double*)xcalloc(m, 8);
+  int rc = 0;
+  for (int k = 0; k < m && !rc; ++k) {
+    for (int w = 0; w < s->h; ++w)
+      for (int j = 0; j < s->nb[w]; ++j) {
+        int n = 0;
+        for (int i = 0; i < m; ++i)
+          if (i != k) t[n++] = s->pieces[w * m + i][j];
+        reps[w][j] = tree_sum64(t, n) / (double)n;
+      }
+    double* R = Rk + (size_t)k * s->nbins;
+    rc = orc_stitch(s->h, s->lo, s->hi, (const double* const*)reps,
+                    (const uint8_t* const*)s->U, s->nbins, R, NULL);
+    if (!rc) rc = orc_normalise(s->model, s->N, s->q, s->nbins, R);
+  }
+  for (int b = 0; b < s->nbins && !rc; ++b) {
+    int fin = 1;
+    double acc = 0.0;
+    for (int k = 0; k < m; ++k) {
+      fin &= isfinite(Rk[(size_t)k * s->nbins + b]) != 0;
+      acc += Rk[(size_t)k * s->nbins + b];
+    }
+    if (!fin) { mean[b] = -INFINITY; err[b] = 0.0; continue; }
+    double mu = acc / (double)m, v = 0.0;
+    for (int k = 0; k < m; ++k) {
+      double d = Rk[(size_t)k * s->nbins + b] - mu;
+      v += d * d;
+    }
+    mean[b] = mu;
+    err[b] = sqrt((double)(m - 1) / (double)m * v);
+  }
+  for (int w = 0; w < s->h; ++w) free(reps[w]);
+  free(reps); free(Rk); free(t);
   return rc;
 }
 

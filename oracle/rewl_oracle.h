@@ -53,7 +53,11 @@ typedef struct {
   uint64_t seed;              /* Philox key */
   int32_t precision;          /* ORC_FP64 or ORC_FP32C */
   int32_t instance;           /* instance index folded into RNG counters */
+  int32_t schedule;           /* ORC_HALVING (flatness + f -> sqrt f) or ORC_ONE_OVER_T */
+  int32_t reserved;
 } orc_params;
+
+enum { ORC_HALVING = 0, ORC_ONE_OVER_T = 1 };
 
 typedef struct {
   int32_t N, nbins, binw, emin, h, m, W;
@@ -101,6 +105,16 @@ int orc_get_window(const orc_sim* s, int32_t w, double* lnf, int32_t* stage,
                    int32_t* frozen, uint8_t* U, int64_t* stage_merge);
 /* Per lower window w of a pair (w, w+1): proposals, proposals with both
  * energies inside the partner window, accepted swaps. */
+/* Statistical errors of the joined, normalised ln g by the jackknife over
+ * the m walkers of every window (Sec. 3): piece k of window w is the
+ * average of the walkers' ln g captured just before the merge that froze the
+ * window, leaving walker k out; the m leave-one-out joins give mean and
+ * error per bin.  Needs every window frozen and m >= 2; -1 otherwise. */
+int orc_jackknife(const orc_sim* s, double* mean, double* err);
+/* Schedule phase of window w (0 halving, 1 ln f = 1/t), -1 on bad input. */
+int orc_get_phase(const orc_sim* s, int32_t w);
+/* ln g of walker `slot` captured before its window's freezing merge. */
+int orc_get_piece(const orc_sim* s, int32_t slot, double* out);
 int orc_get_exchange_stats(const orc_sim* s, uint64_t* tries, uint64_t* in_range, uint64_t* accepts);
 
 /* Joined and normalised ln g over all nbins (-inf where no window visited);

@@ -26,12 +26,12 @@ MUTANTS = [
      "double lnP = (s->lng[si][ix] - s->lng[si][iy]) + (s->lng[sj][jx] - s->lng[sj][jy]);",
      "tests/test_oracle_rewl.py::test_fixed_lng_stationary_distribution_with_exchanges"),
     ("histogram_not_reset_at_merge",
-     "      for (int k = 0; k < m; ++k) s->H[w * m + k][j] = 0;\n",
+     "    for (int k = 0; k < m; ++k) s->H[w * m + k][j] = 0;\n",
      "",
      "tests/test_oracle_rewl.py::test_histogram_counts_attempts_and_merge_semantics"),
     ("lnf_not_halved",
-     "    s->lnf[w] *= 0.5;\n",
-     "    s->lnf[w] *= 0.75;\n",
+     "double next = phase_b ? tinv : 0.5 * s->lnf[w];",
+     "double next = phase_b ? tinv : 0.75 * s->lnf[w];",
      "tests/test_oracle_rewl.py::test_histogram_counts_attempts_and_merge_semantics"),
     ("merge_wrong_divisor",
      "double mean = tree_sum64(t64, m) / (double)m;",
@@ -53,6 +53,22 @@ MUTANTS = [
      "if ((uint64_t)s->p.flat_den * cnt * mn < (uint64_t)s->p.flat_num * sum) ready = 0;",
      "if ((uint64_t)s->p.flat_num * cnt * mn < (uint64_t)s->p.flat_den * sum) ready = 0;",
      "tests/test_oracle_rewl.py::test_histogram_counts_attempts_and_merge_semantics"),
+    ("one_over_t_value",
+     "double tinv = (double)cnt / (double)s->att[w * m];",
+     "double tinv = (double)(cnt + 1) / (double)s->att[w * m];",
+     "tests/test_oracle_schedule.py::test_one_over_t_schedule_follows_its_definition"),
+    ("one_over_t_late_switch",
+     "int to_b = s->p.schedule == ORC_ONE_OVER_T && !phase_b && next <= tinv;",
+     "int to_b = s->p.schedule == ORC_ONE_OVER_T && !phase_b && next <= 0.5 * tinv;",
+     "tests/test_oracle_schedule.py::test_one_over_t_schedule_follows_its_definition"),
+    ("jackknife_variance_factor",
+     "err[b] = sqrt((double)(m - 1) / (double)m * v);",
+     "err[b] = sqrt(v / (double)m);",
+     "tests/test_oracle_schedule.py::test_jackknife_single_window_is_standard_error_of_mean"),
+    ("pieces_wrong_walker",
+     "s->pieces[w * m + k][j] = lng_at(s, w * m + k, j);",
+     "s->pieces[w * m + k][j] = lng_at(s, w * m, j);",
+     "tests/test_oracle_schedule.py::test_pieces_are_the_walkers_before_the_freezing_merge"),
     ("energy_neighbour_index",
      "int sd = sp[((y + 1) % L) * L + x];",
      "int sd = sp[((y + 1) % L) * L + (x + 1) % L];",
