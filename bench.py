@@ -13,12 +13,12 @@ Printed: one JSON line with spin-flip attempts/s, the sweep kernel's
 roofline position (kernel time from HIP events recorded on the library's
 stream) and the single-threaded CPU oracle's attempts/s on a bounded sample.
 
---converge --config {cfg1,cfg2,cfg3,cfg34} runs R copies of a configuration
-to ln f <= ln f_final and reports time to convergence and accuracy: Ising
-against the exact density of states, Potts by the sum rule, exact
-low-energy counts and the C_V peak; cfg34 runs the q=10 Potts instances in
+--converge --config {cfg1,cfg2,cfg3,cfg34} [--schedule halving|1t] runs R
+copies of a configuration to ln f <= ln f_final and reports time to
+convergence and the C_V peak (Potts); cfg34 runs the q=10 Potts instances in
 FP64 and in two-float FP32 and compares them (progress lines precede the
-JSON line).
+JSON line).  --save keeps the normalised ln g and jackknife errors for
+scoring against exact results by tests/converge_report.py.
 """
 import argparse
 import hashlib
@@ -66,6 +66,10 @@ def parse():
     ap.add_argument("--converge", action="store_true")
     ap.add_argument("--config", choices=["cfg1", "cfg2", "cfg3", "cfg34"], default="cfg2")
     ap.add_argument("--max-minutes", type=float, default=50.0)
+    ap.add_argument("--schedule", choices=["halving", "1t"], default="halving")
+    ap.add_argument("--lnf-final", type=float, default=0.0,
+                    help="override ln f_final of the configuration (--converge)")
+    ap.add_argument("--save", default="", help="npz for ln g and jackknife errors (--converge)")
     ap.add_argument("--copy-reference", action="store_true",
                     help="only copy a 512 MiB device buffer 3 times (HBM counter calibration)")
     return ap.parse_args()
@@ -147,52 +151,48 @@ def cv_peak(ctx, i, T):
 
 def converge(a):
     """Runs R instances of a configuration to ln f <= lnf_final and reports
-    time to convergence and accuracy (Ising: against the exact DOS; Potts:
-    sum rule and exact low-energy counts, C_V peak; --config cfg34 also runs
-    the two-float FP32 form on the same instances and compares)."""
-    from oracle import exact_dos
+    time to convergence, C_V peaks (Potts) and, for --config cfg34, the
+    two-float FP32 form against FP64 on the same instances.  The normalised
+    ln g and jackknife errors of every finished instance are saved to
+    --save (an .npz); tests/converge_report.py scores them against exact
+    results."""
     from paper_1402_2328_amd import rewl
     from paper_1402_2328_amd import workloads as WL
-    from tests.test_oracle_exact import load_ising_table
     name = a.config
     R = a.replicas
     runs = {"cfg1": [("fp64", WL.CFG1)], "cfg2": [("fp64", WL.CFG2)], "cfg3": [("fp64", WL.CFG3)],
             "cfg34": [("fp64", WL.CFG3), ("fp32c", WL.CFG4)]}[name]
-    out = {"metric": "time to ln f <= ln f_final and accuracy of ln g", "config": name,
+    sched = WL.ONE_OVER_T if a.schedule == "1t" else WL.HALVING
+    out = {"metric": "time to ln f <= ln f_final", "config": name, "schedule": a.schedule,
            "instances": R, "runs": {}}
+    saved = {}
     lng_by_run = {}
     for tag, cfg in runs:
+        cfg = dict(cfg, schedule=sched)
+        if a.lnf_final > 0:
+            cfg["lnf_final"] = a.lnf_final
         ctx = rewl.Context([WL.rewl_params_of(cfg)] * R)
         plan = ctx.autotune(cfg["flips_per_exchange"])
         done_at, cycles, wall = run_to_convergence(ctx, R, cfg["flips_per_exchange"],
                                                    a.max_minutes * 60 / len(runs), tag)
         g = ctx.geometry[0]
-        N, nb = g["N"], g["nbins"]
-        res = {"precision": tag, "launch": plan, "converged": len(done_at), "cycles_run": cycles,
-               "wall_s_all": wall,
+        N = g["N"]
+        res = {"precision": tag, "lnf_final": cfg["lnf_final"], "launch": plan,
+               "converged": len(done_at), "cycles_run": cycles, "wall_s_all": wall,
                "wall_s_median": float(np.median(list(done_at.values()))) if done_at else None,
                "cycles_to_converge": sorted(int(ctx.status(i)["done_merge"]) for i in done_at)}
-        lngs = {i: ctx.get_lng(i)[0] for i in sorted(done_at)}
+        ids = sorted(done_at)
+        lngs = {i: ctx.get_lng(i)[0] for i in ids}
         lng_by_run[tag] = lngs
-        if cfg["model"] == WL.ISING and lngs:
-            exact = exact_dos.ln_g(load_ising_table(cfg["L"]))
-            fin = np.isfinite(exact)
-            errs = [float(np.max(np.abs(v[fin] - exact[fin]))) for v in lngs.values()]
-            res.update({"max_abs_err_vs_exact": errs, "median_max_abs_err": float(np.median(errs))})
-        elif lngs:
-            q = cfg["q"]
-            low = exact_dos.potts_low_energy(q, cfg["L"])
-            sums, lows, peaks = [], [], []
+        if ids:
+            saved[f"{tag}_instances"] = np.array(ids)
+            saved[f"{tag}_lng"] = np.array([lngs[i] for i in ids])
+            if cfg["walkers_per_window"] > 1:
+                saved[f"{tag}_jk_err"] = np.array([ctx.jackknife(i)[1] for i in ids])
+        if cfg["model"] == WL.POTTS and ids:
             T = np.arange(0.60, 0.80, 1e-4)
-            for i, v in lngs.items():
-                fin = np.isfinite(v)
-                mx = np.max(v[fin])
-                sums.append(float(mx + np.log(np.sum(np.exp(v[fin] - mx))) - N * np.log(q)))
-                lows.append(max(abs(v[j] - np.log(c)) for j, c in low.items() if c))
-                Tp, Cp = cv_peak(ctx, i, T)
-                peaks.append((Tp, Cp / N))
-            res.update({"lse_minus_N_ln_q": sums, "max_abs_err_low_energy_counts": lows,
-                        "cv_peak_T_and_height_per_spin": peaks})
+            res["cv_peak_T_and_height_per_spin"] = [
+                (lambda tp: (tp[0], tp[1] / N))(cv_peak(ctx, i, T)) for i in ids]
         out["runs"][tag] = res
         ctx.close()
     if "fp32c" in lng_by_run and "fp64" in lng_by_run:
@@ -210,6 +210,11 @@ def converge(a):
             dd.append(float(np.max(np.abs(a64[x][fin] - a64[y][fin]))))
         out["fp32c_vs_fp64_max_abs_diff"] = d
         out["fp64_vs_fp64_independent_max_abs_diff"] = dd
+    if a.save:
+        os.makedirs(os.path.dirname(os.path.abspath(a.save)), exist_ok=True)
+        np.savez(a.save, config=name, model=runs[0][1]["model"], L=runs[0][1]["L"],
+                 q=runs[0][1]["q"], **saved)
+        out["saved"] = a.save
     return out
 
 

@@ -66,6 +66,14 @@ enum {
 
 enum { REWL_ISING = 0, REWL_POTTS = 1 };
 enum { REWL_FP64 = 0, REWL_FP32C = 1 };
+/* ln f schedules.  HALVING (Sec. 2): when all m walkers of a window are flat
+ * their ln g are merged, H is reset and ln f halves.  ONE_OVER_T, the "1/t"
+ * rule (Belardinelli and Pereyra) that Sec. 2 names as compatible with REWL:
+ * phase A halves ln f, with the same merge, once every walker of the window
+ * has visited every bin of the window's visited union; once halving would
+ * bring ln f to or below 1/t, t = MC attempts per walker / visited bins, the
+ * window switches to phase B, where every check sets ln f = 1/t and merges. */
+enum { REWL_HALVING = 0, REWL_ONE_OVER_T = 1 };
 
 /* One REWL instance.  All instances of one context must share `precision`. */
 typedef struct {
@@ -83,6 +91,8 @@ typedef struct {
   double lnf_final;           /* window frozen once ln f <= lnf_final */
   int64_t flips_per_exchange; /* F: attempts per walker per cycle (informative) */
   uint64_t seed;              /* Philox4x32-10 key */
+  int32_t schedule;           /* REWL_HALVING or REWL_ONE_OVER_T */
+  int32_t reserved;           /* must be 0 */
 } rewl_params;
 
 typedef struct rewl_ctx rewl_ctx;
@@ -133,7 +143,10 @@ int rewl_autotune(rewl_ctx* ctx, int64_t flips, int32_t repeats, int32_t* out);
 /* Enqueues the flatness test and in-window merge for every non-frozen window
  * (Sec. 2): when all m walkers of a window are flat at this check, their ln g
  * are averaged (pairwise sum in walker order, divided by m), H is reset and
- * ln f halves; the window freezes once ln f <= lnf_final.  An instance whose
+ * ln f halves; the window freezes once ln f <= lnf_final.  Under the 1/t
+ * schedule the readiness test and the new ln f follow REWL_ONE_OVER_T.  The
+ * walkers' ln g just before the merge that freezes a window are kept as the
+ * window's m pieces (rewl_get_piece, rewl_jackknife).  An instance whose
  * windows are all frozen is finished.  Errors: HIP. */
 int rewl_merge(rewl_ctx* ctx);
 
@@ -194,6 +207,28 @@ int rewl_get_visited(rewl_ctx* ctx, int32_t instance, int32_t window, uint8_t* m
  * with both energies inside the partner window, accepted swaps (h entries). */
 int rewl_get_exchange_stats(rewl_ctx* ctx, int32_t instance, uint64_t* tries,
                             uint64_t* in_range, uint64_t* accepts);
+
+/* Synchronises.  phase: NULL or n_windows entries (0 = halving phase, 1 =
+ * ln f = 1/t phase); stage_merge: NULL or n_windows * 64 entries, entry
+ * w * 64 + s = merge index at which window w finished WL iteration s (-1 if
+ * not yet).  Errors: INVAL, HIP. */
+int rewl_get_schedule(rewl_ctx* ctx, int32_t instance, int32_t* phase, int64_t* stage_merge);
+
+/* Synchronises.  ln g (FP64; FP32C hi + lo widened) of walker `slot`
+ * (w*m + k) just before the merge that froze its window: nb_w doubles, zero
+ * while the window is not frozen.  Errors: INVAL, HIP. */
+int rewl_get_piece(rewl_ctx* ctx, int32_t instance, int32_t slot, double* host_lng);
+
+/* Synchronises.  Jackknife error bars of the joined, normalised ln g over
+ * the m pieces per window (Sec. 3): for k = 0..m-1 each window's
+ * representative is the mean of its pieces without walker k (pairwise sum in
+ * walker order, divided by m-1); the h representatives are joined and
+ * normalised as in rewl_get_lng, giving R_k.  Per bin: mean = sum R_k / m,
+ * err = sqrt((m-1)/m * sum (R_k - mean)^2); where any R_k is -inf, mean =
+ * -inf and err = 0.  mean, err: capacity doubles each, nbins used.  Errors:
+ * INVAL (capacity), STATE (instance not finished, or m < 2), HIP. */
+int rewl_jackknife(rewl_ctx* ctx, int32_t instance, double* host_mean, double* host_err,
+                   int32_t capacity, int32_t* n_bins_out);
 
 /* Synchronises.  Canonical <E> and C_V (Eqs. 5-6, k_B = 1) from the joined,
  * normalised ln g of an instance, evaluated on the GPU in FP64 for nT

@@ -43,8 +43,9 @@ struct Layout {
   int32_t walkers[3] = {0, 0, 0};
   int32_t prec = 0;
   // byte offsets inside the workspace
+  int64_t jk_elems = 0;  // largest (m + 2) * nbins of any instance
   size_t o_inst, o_win, o_wg, o_ist, o_wst, o_sm, o_xs, o_cfg, o_E, o_att, o_watt, o_spins,
-      o_lng, o_lhi, o_llo, o_H, o_U, o_rep, o_R, o_thermo, o_joins, total;
+      o_lng, o_lhi, o_llo, o_H, o_pieces, o_U, o_rep, o_R, o_thermo, o_joins, o_jk, total;
 };
 
 // Equal-size windows with overlap num/den over bins 0..nbins-1 (Fig. 1a):
@@ -68,6 +69,8 @@ int check_params(const rewl_params& p) {
   if (p.precision != REWL_FP64 && p.precision != REWL_FP32C) return REWL_E_INVAL;
   if (!(p.lnf_init > 0.0) || !(p.lnf_final > 0.0) || !isfinite(p.lnf_init)) return REWL_E_INVAL;
   if (p.overlap_den <= 0 || p.overlap_num < 0 || p.overlap_num >= p.overlap_den) return REWL_E_INVAL;
+  if (p.schedule != REWL_HALVING && p.schedule != REWL_ONE_OVER_T) return REWL_E_INVAL;
+  if (p.reserved != 0) return REWL_E_INVAL;
   return REWL_OK;
 }
 
@@ -116,6 +119,7 @@ int build_layout(const rewl_params* params, int32_t n, const int32_t* wlo, const
     I.key0 = (uint32_t)p.seed;
     I.key1 = (uint32_t)(p.seed >> 32);
     I.invL = 1.0f / (float)p.L;
+    I.schedule = p.schedule;
     I.r_base = rbase;
     I.rep_base = rep;
     std::vector<int32_t> lo(I.h), hi(I.h);
@@ -157,6 +161,7 @@ int build_layout(const rewl_params* params, int32_t n, const int32_t* wlo, const
     win += I.h;
     spin += (int64_t)I.W * I.npad;
     rbase += I.nbins;
+    Lo.jk_elems = std::max(Lo.jk_elems, (int64_t)(I.m + 2) * I.nbins);
     Lo.inst.push_back(I);
   }
   Lo.n_slots = slot;
@@ -193,11 +198,13 @@ int build_layout(const rewl_params* params, int32_t n, const int32_t* wlo, const
     Lo.o_llo = take(sizeof(float) * lng);
   }
   Lo.o_H = take(sizeof(uint32_t) * lng);
+  Lo.o_pieces = take(sizeof(double) * lng);
   Lo.o_U = take((size_t)Lo.u_elems);
   Lo.o_rep = take(sizeof(double) * rep);
   Lo.o_R = take(sizeof(double) * rbase);
   Lo.o_thermo = take(sizeof(double) * 3 * kMaxTemps);
   Lo.o_joins = take(sizeof(int32_t) * nw);
+  Lo.o_jk = take(sizeof(double) * (size_t)Lo.jk_elems);
   Lo.total = o;
   return REWL_OK;
 }
@@ -322,11 +329,13 @@ void fill_ptrs(rewl_ctx* c) {
   P.lhi = L.prec == REWL_FP32C ? at<float>(c, L.o_lhi) : nullptr;
   P.llo = L.prec == REWL_FP32C ? at<float>(c, L.o_llo) : nullptr;
   P.H = at<uint32_t>(c, L.o_H);
+  P.pieces = at<double>(c, L.o_pieces);
   P.U = at<uint8_t>(c, L.o_U);
   P.rep = at<double>(c, L.o_rep);
   P.R = at<double>(c, L.o_R);
   P.thermo = at<double>(c, L.o_thermo);
   P.joins = at<int32_t>(c, L.o_joins);
+  P.jk = at<double>(c, L.o_jk);
   P.n_inst = (int32_t)L.inst.size();
   P.n_win = (int32_t)L.win.size();
   P.n_slots = L.n_slots;
@@ -423,6 +432,8 @@ int rewl_init(const rewl_params* params, int32_t n, const int32_t* win_lo, const
       s.lnf = p.lnf_init;
       s.stage = 0;
       s.frozen = p.lnf_init <= p.lnf_final;
+      s.phase = 0;
+      s.pad = 0;
       all &= s.frozen;
     }
     is[i].done = all;
@@ -766,6 +777,46 @@ int rewl_get_lng(rewl_ctx* c, int32_t instance, int32_t which, double* out, int3
   if (rc) return rc;
   rc = d2h(c, out, c->P.R + I.r_base, (size_t)I.nbins);
   if (!rc && joins && I.h > 1) rc = d2h(c, joins, c->P.joins + I.win_base + 1, (size_t)(I.h - 1));
+  return rc;
+}
+
+int rewl_get_schedule(rewl_ctx* c, int32_t instance, int32_t* phase, int64_t* stage_merge) {
+  if (!c || instance < 0 || instance >= (int32_t)c->lo.inst.size()) return REWL_E_INVAL;
+  const InstDesc& I = c->lo.inst[instance];
+  int rc = REWL_OK;
+  if (phase) {
+    std::vector<WinState> ws(I.h);
+    rc = d2h(c, ws.data(), c->P.wst + I.win_base, (size_t)I.h);
+    for (int w = 0; w < I.h && !rc; ++w) phase[w] = ws[w].phase;
+  }
+  if (!rc && stage_merge)
+    rc = d2h(c, stage_merge, c->P.stage_merge + (int64_t)I.win_base * kMaxStages,
+             (size_t)I.h * kMaxStages);
+  return rc;
+}
+
+int rewl_get_piece(rewl_ctx* c, int32_t instance, int32_t slot, double* lng) {
+  if (!c || !lng || instance < 0 || instance >= (int32_t)c->lo.inst.size()) return REWL_E_INVAL;
+  const InstDesc& I = c->lo.inst[instance];
+  if (slot < 0 || slot >= I.W) return REWL_E_INVAL;
+  const WinDesc& W = c->lo.win[I.win_base + slot / I.m];
+  return d2h(c, lng, c->P.pieces + W.lng_base + (int64_t)(slot % I.m) * W.nb, (size_t)W.nb);
+}
+
+int rewl_jackknife(rewl_ctx* c, int32_t instance, double* mean, double* err, int32_t capacity,
+                   int32_t* n_bins_out) {
+  if (!c || !mean || !err || instance < 0 || instance >= (int32_t)c->lo.inst.size()) return REWL_E_INVAL;
+  const InstDesc& I = c->lo.inst[instance];
+  if (n_bins_out) *n_bins_out = I.nbins;
+  if (capacity < I.nbins) return REWL_E_INVAL;
+  if (I.m < 2) return REWL_E_STATE;
+  InstState st;
+  int rc = d2h(c, &st, c->P.ist + instance, 1);
+  if (rc) return rc;
+  if (!st.done) return REWL_E_STATE;
+  rc = hip_rc(launch_jackknife(c->P, instance, c->stream));
+  if (!rc) rc = d2h(c, mean, c->P.jk + (int64_t)I.m * I.nbins, (size_t)I.nbins);
+  if (!rc) rc = d2h(c, err, c->P.jk + (int64_t)(I.m + 1) * I.nbins, (size_t)I.nbins);
   return rc;
 }
 

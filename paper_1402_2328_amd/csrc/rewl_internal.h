@@ -20,6 +20,7 @@ constexpr int kMinPageBins = 16;  // smallest ln g page the launch planner picks
 
 enum Model : int32_t { kIsing = 0, kPotts = 1 };
 enum Prec : int32_t { kFP64 = 0, kFP32C = 1 };
+enum Schedule : int32_t { kHalving = 0, kOneOverT = 1 };
 enum Tag : uint32_t { kTagMC = 0, kTagPerm = 1, kTagAcc = 2, kTagWarm = 3, kTagInit = 4 };
 
 struct InstDesc {
@@ -35,7 +36,7 @@ struct InstDesc {
   double lnf_final;
   uint32_t key0, key1;
   float invL;
-  int32_t pad0;
+  int32_t schedule;      // kHalving or kOneOverT
 };
 
 struct WinDesc {
@@ -48,6 +49,8 @@ struct WinDesc {
 struct WinState {
   double lnf;
   int32_t stage, frozen;
+  int32_t phase;         // 1/t schedule: 0 = halving phase, 1 = ln f = 1/t
+  int32_t pad;
 };
 
 struct InstState {
@@ -78,11 +81,13 @@ struct DevPtrs {
   float* lhi;                // FP32C two-float ln g
   float* llo;
   uint32_t* H;               // histograms, same indexing as ln g
+  double* pieces;            // ln g of every walker just before its window froze
   uint8_t* U;                // visited-union masks per window
   double* rep;               // window representatives for joining
   double* R;                 // joined ln g per instance
   double* thermo;            // [3][kMaxTemps]: T, <E>, C_V
   int32_t* joins;            // [windows] join bin of (w-1, w)
+  double* jk;                // jackknife scratch: (m + 2) x nbins of one instance
   int32_t n_inst, n_win, n_slots, n_wg;
   int32_t prec;
   int32_t pad;
@@ -104,6 +109,9 @@ hipError_t launch_sweep_class(const DevPtrs& P, int cls, SweepShape sh, int32_t 
 hipError_t launch_merge(const DevPtrs& P, hipStream_t s);
 hipError_t launch_exchange(const DevPtrs& P, hipStream_t s);
 hipError_t launch_join(const DevPtrs& P, int32_t instance, int32_t normalise, hipStream_t s);
+// Leave-one-out joins of an instance's frozen pieces; mean and error land
+// in rows m and m + 1 of P.jk.
+hipError_t launch_jackknife(const DevPtrs& P, int32_t instance, hipStream_t s);
 hipError_t launch_thermo(const DevPtrs& P, int32_t instance, int32_t nT, hipStream_t s);
 hipError_t prepare_sweep_lds(size_t lds_bytes);
 

@@ -4,8 +4,8 @@
 // Once per cycle: k_merge_windows (flatness by block reductions
 // and the in-window average), k_merge_finish, k_exchange (Eq. 1, swaps
 // configuration indices, never lattice data), k_exchange_finish.  End of
-// run: k_join (Sec. 3 joining + normalisation in FP64) and k_thermo
-// (Eqs. 5-6).
+// run: k_join (Sec. 3 joining + normalisation in FP64), k_jackknife
+// (error bars from the m pieces per window) and k_thermo (Eqs. 5-6).
 #include <float.h>
 #include <math.h>
 
@@ -139,11 +139,11 @@ __global__ void k_init(DevPtrs P) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_merge_windows(DevPtrs P) {
   __shared__ uint64_t red64[8];
-  __shared__ int ready_s;
   const int gw = blockIdx.x;
   const WinDesc W = P.win[gw];
   const InstDesc& I = P.inst[W.inst];
-  if (P.ist[W.inst].done || P.ist[W.inst].error || P.wst[gw].frozen) return;
+  const WinState ws0 = P.wst[gw];
+  if (P.ist[W.inst].done || P.ist[W.inst].error || ws0.frozen) return;
   const int m = I.m, nb = W.nb;
   const int tid = threadIdx.x;
   uint8_t* U = P.U + W.u_base;
@@ -157,8 +157,10 @@ __global__ __launch_bounds__(256) void k_merge_windows(DevPtrs P) {
     cnt += u;
   }
   cnt = block_reduce(cnt, [](uint64_t a, uint64_t b) { return a + b; }, red64);
+  const bool one_t = I.schedule == kOneOverT;
+  const bool phase_b = one_t && ws0.phase == 1;
   bool ready = cnt > 0;
-  for (int k = 0; k < m && ready; ++k) {
+  for (int k = 0; k < m && ready && !phase_b; ++k) {
     uint64_t mn = UINT64_MAX, sm = 0;
     for (int j = tid; j < nb; j += blockDim.x) {
       const uint64_t h = P.H[W.lng_base + (int64_t)k * nb + j];
@@ -168,14 +170,30 @@ __global__ __launch_bounds__(256) void k_merge_windows(DevPtrs P) {
     }
     mn = block_reduce(mn, [](uint64_t a, uint64_t b) { return a < b ? a : b; }, red64);
     sm = block_reduce(sm, [](uint64_t a, uint64_t b) { return a + b; }, red64);
-    if ((uint64_t)I.flat_den * cnt * mn < (uint64_t)I.flat_num * sm) ready = false;
+    if (one_t) {
+      if (mn == 0) ready = false;
+    } else if ((uint64_t)I.flat_den * cnt * mn < (uint64_t)I.flat_num * sm) {
+      ready = false;
+    }
   }
   if (!ready) return;
+
+  // new ln f: halve (phase A / halving schedule), or 1/t with t the attempts
+  // per walker over the visited bins; phase A hands over to B once halving
+  // would reach 1/t
+  const int slot0 = I.slot_base + (gw - I.win_base) * m;
+  const double tinv = (double)cnt / (double)P.att[slot0];
+  double next = phase_b ? tinv : 0.5 * ws0.lnf;
+  const bool to_b = one_t && !phase_b && next <= tinv;
+  if (to_b) next = tinv;
+  const bool freezing = next <= I.lnf_final;
 
   for (int j = tid; j < nb; j += blockDim.x) {
     if (P.prec == kFP64) {
       double v[kMaxWalkersPerWindow];
       for (int k = 0; k < m; ++k) v[k] = P.lng[W.lng_base + (int64_t)k * nb + j];
+      if (freezing)
+        for (int k = 0; k < m; ++k) P.pieces[W.lng_base + (int64_t)k * nb + j] = v[k];
       int n = m;
       while (n > 1) {
         int o = 0;
@@ -192,6 +210,9 @@ __global__ __launch_bounds__(256) void k_merge_windows(DevPtrs P) {
         vh[k] = P.lhi[W.lng_base + (int64_t)k * nb + j];
         vl[k] = P.llo[W.lng_base + (int64_t)k * nb + j];
       }
+      if (freezing)
+        for (int k = 0; k < m; ++k)
+          P.pieces[W.lng_base + (int64_t)k * nb + j] = (double)vh[k] + (double)vl[k];
       int n = m;
       while (n > 1) {
         int o = 0;
@@ -220,14 +241,16 @@ __global__ __launch_bounds__(256) void k_merge_windows(DevPtrs P) {
     for (int k = 0; k < m; ++k) P.H[W.lng_base + (int64_t)k * nb + j] = 0;
   }
   if (tid == 0) {
-    WinState ws = P.wst[gw];
-    if (ws.stage < kMaxStages) P.stage_merge[(int64_t)gw * kMaxStages + ws.stage] = P.ist[W.inst].merges;
-    ws.stage += 1;
-    ws.lnf *= 0.5;
-    if (ws.lnf <= I.lnf_final) ws.frozen = 1;
+    WinState ws = ws0;
+    if (!phase_b) {
+      if (ws.stage < kMaxStages) P.stage_merge[(int64_t)gw * kMaxStages + ws.stage] = P.ist[W.inst].merges;
+      ws.stage += 1;
+    }
+    ws.lnf = next;
+    if (to_b) ws.phase = 1;
+    if (freezing) ws.frozen = 1;
     P.wst[gw] = ws;
   }
-  (void)ready_s;
 }
 
 __global__ void k_merge_finish(DevPtrs P) {
@@ -337,6 +360,85 @@ __device__ __forceinline__ double beta5(const double* l, int j) {
   return (((l[j - 2] - 8.0 * l[j - 1]) + 8.0 * l[j + 1]) - l[j + 2]) / 12.0;
 }
 
+// Joins the window representatives in P.rep into R (Sec. 3, Eq. 2): the
+// first window as it is, then window w from the bin of (w-1, w) where the
+// five-point slopes agree best (lowest such bin on ties; the middle of the
+// overlap if no bin qualifies), shifted to continue the joined curve.
+// normalise: Ising sum g = 2^N, Potts g(E_min) = q.  Whole block.
+__device__ void stitch_normalise(const DevPtrs& P, const InstDesc& I, double* R, int normalise,
+                                 double* redd, int64_t* redi, double& shift_s, int& best_s,
+                                 bool record_joins) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  __syncthreads();
+  for (int b = tid; b < I.nbins; b += nt) R[b] = -INFINITY;
+  __syncthreads();
+  {
+    const WinDesc W0 = P.win[I.win_base];
+    const uint8_t* U0 = P.U + W0.u_base;
+    const double* r0 = P.rep + W0.rep_off;
+    for (int j = tid; j < W0.nb; j += nt) R[W0.lo + j] = U0[j] ? r0[j] : -INFINITY;
+  }
+  if (tid == 0) shift_s = 0.0;
+  __syncthreads();
+  for (int w = 1; w < I.h; ++w) {
+    const WinDesc Wa = P.win[I.win_base + w - 1];
+    const WinDesc Wb = P.win[I.win_base + w];
+    const double* la = P.rep + Wa.rep_off;
+    const double* lb = P.rep + Wb.rep_off;
+    const uint8_t* Ua = P.U + Wa.u_base;
+    const uint8_t* Ub = P.U + Wb.u_base;
+    double bestd = INFINITY;
+    for (int b = Wb.lo + 2 + tid; b <= Wa.hi - 2; b += nt) {
+      bool ok = true;
+      for (int d = -2; d <= 2 && ok; ++d) ok = Ua[b + d - Wa.lo] && Ub[b + d - Wb.lo];
+      if (!ok) continue;
+      const double db = fabs(beta5(la, b - Wa.lo) - beta5(lb, b - Wb.lo));
+      if (db < bestd) bestd = db;
+    }
+    bestd = block_reduce(bestd, [](double a, double b) { return a < b ? a : b; }, redd);
+    int64_t bi = INT64_MAX;
+    if (bestd < INFINITY) {
+      for (int b = Wb.lo + 2 + tid; b <= Wa.hi - 2; b += nt) {
+        bool ok = true;
+        for (int d = -2; d <= 2 && ok; ++d) ok = Ua[b + d - Wa.lo] && Ub[b + d - Wb.lo];
+        if (!ok) continue;
+        const double db = fabs(beta5(la, b - Wa.lo) - beta5(lb, b - Wb.lo));
+        if (db == bestd && b < bi) bi = b;
+      }
+    }
+    bi = block_reduce(bi, [](int64_t a, int64_t b) { return a < b ? a : b; }, redi);
+    if (tid == 0) {
+      const int best = (bi == INT64_MAX) ? (Wb.lo + Wa.hi) / 2 : (int)bi;
+      best_s = best;
+      shift_s = (la[best - Wa.lo] + shift_s) - lb[best - Wb.lo];
+      if (record_joins) P.joins[I.win_base + w] = best;
+    }
+    __syncthreads();
+    const int best = best_s;
+    const double sh = shift_s;
+    for (int b = best + tid; b <= Wb.hi; b += nt)
+      R[b] = Ub[b - Wb.lo] ? lb[b - Wb.lo] + sh : -INFINITY;
+    __syncthreads();
+  }
+  if (!normalise) return;
+  double c;
+  if (I.model == kIsing) {
+    double mx = -INFINITY;
+    for (int b = tid; b < I.nbins; b += nt) mx = fmax(mx, R[b]);
+    mx = block_reduce(mx, [](double a, double b) { return a > b ? a : b; }, redd);
+    double acc = 0.0;
+    for (int b = tid; b < I.nbins; b += nt)
+      if (isfinite(R[b])) acc += exp(R[b] - mx);
+    acc = block_reduce(acc, [](double a, double b) { return a + b; }, redd);
+    c = (double)I.N * log(2.0) - (mx + log(acc));
+  } else {
+    c = log((double)I.q) - R[0];
+  }
+  __syncthreads();
+  for (int b = tid; b < I.nbins; b += nt)
+    if (isfinite(R[b])) R[b] += c;
+}
+
 __global__ __launch_bounds__(256) void k_join(DevPtrs P, int32_t instance, int32_t normalise) {
   __shared__ double redd[8];
   __shared__ int64_t redi[8];
@@ -391,74 +493,66 @@ __global__ __launch_bounds__(256) void k_join(DevPtrs P, int32_t instance, int32
       }
     }
   }
-  __syncthreads();
-  for (int b = tid; b < I.nbins; b += nt) R[b] = -INFINITY;
-  __syncthreads();
-  {
-    const WinDesc W0 = P.win[I.win_base];
-    const uint8_t* U0 = P.U + W0.u_base;
-    const double* r0 = P.rep + W0.rep_off;
-    for (int j = tid; j < W0.nb; j += nt) R[W0.lo + j] = U0[j] ? r0[j] : -INFINITY;
-  }
-  if (tid == 0) shift_s = 0.0;
-  __syncthreads();
-  for (int w = 1; w < I.h; ++w) {
-    const WinDesc Wa = P.win[I.win_base + w - 1];
-    const WinDesc Wb = P.win[I.win_base + w];
-    const double* la = P.rep + Wa.rep_off;
-    const double* lb = P.rep + Wb.rep_off;
-    const uint8_t* Ua = P.U + Wa.u_base;
-    const uint8_t* Ub = P.U + Wb.u_base;
-    double bestd = INFINITY;
-    for (int b = Wb.lo + 2 + tid; b <= Wa.hi - 2; b += nt) {
-      bool ok = true;
-      for (int d = -2; d <= 2 && ok; ++d) ok = Ua[b + d - Wa.lo] && Ub[b + d - Wb.lo];
-      if (!ok) continue;
-      const double db = fabs(beta5(la, b - Wa.lo) - beta5(lb, b - Wb.lo));
-      if (db < bestd) bestd = db;
-    }
-    bestd = block_reduce(bestd, [](double a, double b) { return a < b ? a : b; }, redd);
-    int64_t bi = INT64_MAX;
-    if (bestd < INFINITY) {
-      for (int b = Wb.lo + 2 + tid; b <= Wa.hi - 2; b += nt) {
-        bool ok = true;
-        for (int d = -2; d <= 2 && ok; ++d) ok = Ua[b + d - Wa.lo] && Ub[b + d - Wb.lo];
-        if (!ok) continue;
-        const double db = fabs(beta5(la, b - Wa.lo) - beta5(lb, b - Wb.lo));
-        if (db == bestd && b < bi) bi = b;
+  stitch_normalise(P, I, R, normalise, redd, redi, shift_s, best_s, true);
+}
+
+// Jackknife over the m pieces per window (Sec. 3): for k = 0..m-1 the
+// representatives are the pairwise means of the pieces without walker k,
+// joined and normalised into row k of P.jk; then per bin the mean of the m
+// rows and sqrt((m-1)/m * sum (R_k - mean)^2) go to rows m and m + 1 (-inf
+// and 0 where any row is not finite).  One block.
+__global__ __launch_bounds__(256) void k_jackknife(DevPtrs P, int32_t instance) {
+  __shared__ double redd[8];
+  __shared__ int64_t redi[8];
+  __shared__ double shift_s;
+  __shared__ int best_s;
+  const InstDesc& I = P.inst[instance];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int m = I.m, nbins = I.nbins;
+  for (int k = 0; k < m; ++k) {
+    for (int w = 0; w < I.h; ++w) {
+      const WinDesc W = P.win[I.win_base + w];
+      double* rep = P.rep + W.rep_off;
+      for (int j = tid; j < W.nb; j += nt) {
+        double v[kMaxWalkersPerWindow];
+        int n = 0;
+        for (int i = 0; i < m; ++i)
+          if (i != k) v[n++] = P.pieces[W.lng_base + (int64_t)i * W.nb + j];
+        const int cnt = n;
+        while (n > 1) {
+          int o = 0;
+          for (int i = 0; i + 1 < n; i += 2) v[o++] = v[i] + v[i + 1];
+          if (n & 1) v[o++] = v[n - 1];
+          n = o;
+        }
+        rep[j] = v[0] / (double)cnt;
       }
     }
-    bi = block_reduce(bi, [](int64_t a, int64_t b) { return a < b ? a : b; }, redi);
-    if (tid == 0) {
-      const int best = (bi == INT64_MAX) ? (Wb.lo + Wa.hi) / 2 : (int)bi;
-      best_s = best;
-      shift_s = (la[best - Wa.lo] + shift_s) - lb[best - Wb.lo];
-      P.joins[I.win_base + w] = best;
-    }
     __syncthreads();
-    const int best = best_s;
-    const double sh = shift_s;
-    for (int b = best + tid; b <= Wb.hi; b += nt)
-      R[b] = Ub[b - Wb.lo] ? lb[b - Wb.lo] + sh : -INFINITY;
+    stitch_normalise(P, I, P.jk + (int64_t)k * nbins, 1, redd, redi, shift_s, best_s, false);
     __syncthreads();
   }
-  if (!normalise) return;
-  double c;
-  if (I.model == kIsing) {
-    double mx = -INFINITY;
-    for (int b = tid; b < I.nbins; b += nt) mx = fmax(mx, R[b]);
-    mx = block_reduce(mx, [](double a, double b) { return a > b ? a : b; }, redd);
+  for (int b = tid; b < nbins; b += nt) {
+    bool fin = true;
     double acc = 0.0;
-    for (int b = tid; b < I.nbins; b += nt)
-      if (isfinite(R[b])) acc += exp(R[b] - mx);
-    acc = block_reduce(acc, [](double a, double b) { return a + b; }, redd);
-    c = (double)I.N * log(2.0) - (mx + log(acc));
-  } else {
-    c = log((double)I.q) - R[0];
+    for (int k = 0; k < m; ++k) {
+      const double r = P.jk[(int64_t)k * nbins + b];
+      fin = fin && isfinite(r);
+      acc += r;
+    }
+    double mu = -INFINITY, e = 0.0;
+    if (fin) {
+      mu = acc / (double)m;
+      double v = 0.0;
+      for (int k = 0; k < m; ++k) {
+        const double d = P.jk[(int64_t)k * nbins + b] - mu;
+        v += d * d;
+      }
+      e = sqrt((double)(m - 1) / (double)m * v);
+    }
+    P.jk[(int64_t)m * nbins + b] = mu;
+    P.jk[(int64_t)(m + 1) * nbins + b] = e;
   }
-  __syncthreads();
-  for (int b = tid; b < I.nbins; b += nt)
-    if (isfinite(R[b])) R[b] += c;
 }
 
 // Canonical <E> and C_V (Eqs. 5-6) from the joined ln g: one thread per T.
@@ -517,6 +611,11 @@ hipError_t launch_exchange(const DevPtrs& P, hipStream_t s) {
 
 hipError_t launch_join(const DevPtrs& P, int32_t instance, int32_t normalise, hipStream_t s) {
   hipLaunchKernelGGL(k_join, dim3(1), dim3(256), 0, s, P, instance, normalise);
+  return hipGetLastError();
+}
+
+hipError_t launch_jackknife(const DevPtrs& P, int32_t instance, hipStream_t s) {
+  hipLaunchKernelGGL(k_jackknife, dim3(1), dim3(256), 0, s, P, instance);
   return hipGetLastError();
 }
 

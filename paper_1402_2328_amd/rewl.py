@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "librewl.so")
 
 ISING, POTTS = 0, 1
 FP64, FP32C = 0, 1
+HALVING, ONE_OVER_T = 0, 1
 
 ERRORS = {0: "ok", -1: "invalid argument", -2: "workspace or buffer too small",
           -3: "HIP runtime error", -4: "non-finite ln g", -5: "histogram overflow",
@@ -35,6 +36,7 @@ class rewl_params(C.Structure):
         ("walkers_per_window", C.c_int32), ("flat_num", C.c_int32), ("flat_den", C.c_int32),
         ("precision", C.c_int32), ("lnf_init", C.c_double), ("lnf_final", C.c_double),
         ("flips_per_exchange", C.c_int64), ("seed", C.c_uint64),
+        ("schedule", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -50,7 +52,8 @@ EXPORTS = ["rewl_workspace_bytes", "rewl_init", "rewl_run_sweeps", "rewl_set_lau
            "rewl_exchange", "rewl_run_cycles", "rewl_status", "rewl_running",
            "rewl_get_lng", "rewl_get_geometry", "rewl_get_walker", "rewl_get_walker_f32",
            "rewl_get_visited", "rewl_get_exchange_stats", "rewl_thermo", "rewl_checkpoint",
-           "rewl_restore", "rewl_destroy", "rewl_strerror"]
+           "rewl_restore", "rewl_destroy", "rewl_strerror", "rewl_get_schedule",
+           "rewl_get_piece", "rewl_jackknife"]
 
 
 def lib():
@@ -80,6 +83,9 @@ def lib():
     L.rewl_get_visited.argtypes = [P, I32, I32, P]
     L.rewl_get_exchange_stats.argtypes = [P, I32, P, P, P]
     L.rewl_thermo.argtypes = [P, I32, P, I32, P, P]
+    L.rewl_get_schedule.argtypes = [P, I32, P, P]
+    L.rewl_get_piece.argtypes = [P, I32, I32, P]
+    L.rewl_jackknife.argtypes = [P, I32, P, P, I32, C.POINTER(I32)]
     L.rewl_checkpoint.argtypes = [P, P, SZ, C.POINTER(SZ)]
     L.rewl_restore.argtypes = [P, P, SZ]
     L.rewl_destroy.argtypes = [P]
@@ -100,9 +106,10 @@ def _check(rc, what):
 
 def make_params(model=ISING, L=8, q=2, n_windows=1, overlap=(3, 4), walkers_per_window=1,
                 flat=(4, 5), precision=FP64, lnf_init=1.0, lnf_final=1e-8,
-                flips_per_exchange=10000, seed=1):
+                flips_per_exchange=10000, seed=1, schedule=HALVING):
     return rewl_params(model, L, q, n_windows, overlap[0], overlap[1], walkers_per_window,
-                       flat[0], flat[1], precision, lnf_init, lnf_final, flips_per_exchange, seed)
+                       flat[0], flat[1], precision, lnf_init, lnf_final, flips_per_exchange, seed,
+                       schedule, 0)
 
 
 def _window_arrays(windows):
@@ -264,6 +271,33 @@ class Context:
         _check(lib().rewl_get_exchange_stats(self._h, instance, _p(t), _p(r), _p(a)),
                "rewl_get_exchange_stats")
         return t, r, a
+
+    def get_schedule(self, instance=0):
+        """Per window: phase (0 halving, 1 ln f = 1/t) and the merge index at
+        which each WL iteration ended ([h, 64], -1 if not reached)."""
+        h = self.geometry[instance]["h"]
+        phase = np.zeros(h, np.int32)
+        sm = np.zeros((h, 64), np.int64)
+        _check(lib().rewl_get_schedule(self._h, instance, _p(phase), _p(sm)), "rewl_get_schedule")
+        return phase, sm
+
+    def get_piece(self, instance, slot):
+        g = self.geometry[instance]
+        w = slot // g["m"]
+        out = np.zeros(int(g["hi"][w] - g["lo"][w] + 1), np.float64)
+        _check(lib().rewl_get_piece(self._h, instance, slot, _p(out)), "rewl_get_piece")
+        return out
+
+    def jackknife(self, instance=0):
+        """Jackknife mean and error of the normalised joined ln g over the m
+        pieces per window."""
+        g = self.geometry[instance]
+        mean = np.zeros(g["nbins"], np.float64)
+        err = np.zeros(g["nbins"], np.float64)
+        nb = C.c_int32()
+        _check(lib().rewl_jackknife(self._h, instance, _p(mean), _p(err), len(mean), C.byref(nb)),
+               "rewl_jackknife")
+        return mean, err
 
     def thermo(self, T, instance=0):
         T = np.ascontiguousarray(T, dtype=np.float64)

@@ -10,13 +10,14 @@ import numpy as np
 
 ISING, POTTS = 0, 1
 FP64, FP32C = 0, 1
+HALVING, ONE_OVER_T = 0, 1
 
 
 def config(model, L, q=2, n_windows=1, walkers_per_window=1, lnf_final=1e-8, flips=10000,
-           seed=1, precision=FP64, flat=(4, 5), overlap=(3, 4), lnf_init=1.0):
+           seed=1, precision=FP64, flat=(4, 5), overlap=(3, 4), lnf_init=1.0, schedule=HALVING):
     return dict(model=model, L=L, q=q, n_windows=n_windows, walkers_per_window=walkers_per_window,
                 lnf_final=lnf_final, flips_per_exchange=flips, seed=seed, precision=precision,
-                flat=flat, overlap=overlap, lnf_init=lnf_init)
+                flat=flat, overlap=overlap, lnf_init=lnf_init, schedule=schedule)
 
 
 # Ising L=8: 4 windows x 1 walker, ln f 1 -> 1e-6, exchange every 1000 flips
@@ -74,4 +75,4 @@ def rewl_params_of(cfg):
                             walkers_per_window=cfg["walkers_per_window"], flat=tuple(cfg["flat"]),
                             precision=cfg["precision"], lnf_init=cfg["lnf_init"],
                             lnf_final=cfg["lnf_final"], flips_per_exchange=cfg["flips_per_exchange"],
-                            seed=cfg["seed"])
+                            seed=cfg["seed"], schedule=cfg.get("schedule", HALVING))

@@ -11,7 +11,8 @@ def oracle_sim(cfg, instance=0, windows=None):
                  overlap=tuple(cfg["overlap"]), walkers_per_window=cfg["walkers_per_window"],
                  flat=tuple(cfg["flat"]), lnf_init=cfg["lnf_init"], lnf_final=cfg["lnf_final"],
                  flips_per_exchange=cfg["flips_per_exchange"], seed=cfg["seed"],
-                 precision=cfg["precision"], instance=instance)
+                 precision=cfg["precision"], instance=instance,
+                 schedule=cfg.get("schedule", O.HALVING))
 
 
 def gpu_context(cfgs, windows=None):
@@ -30,7 +31,8 @@ def compare_state(ctx, instance, sim, slots=None, windows=True):
 
     Walker-level: spins of the carried configuration, energy, H, ln g bits
     (FP64, or both two-float parts), attempt counter, configuration identity.
-    Window-level: ln f, stage, frozen flag, visited union.  Instance-level:
+    Window-level: ln f, stage, schedule phase, iteration-end merges, frozen
+    flag, visited union, and the frozen pieces of its walkers.  Instance-level:
     finished flag, merge and round counters, exchange statistics.
     """
     g = ctx.geometry[instance]
@@ -56,11 +58,18 @@ def compare_state(ctx, instance, sim, slots=None, windows=True):
     assert st["done"] == os_["done"]
     assert st["merges"] == os_["merges"] and st["rounds"] == os_["rounds"]
     assert st["done_merge"] == os_["done_merge"]
+    phase, sm = ctx.get_schedule(instance)
     for w in range(g["h"]):
         ow = sim.window(w)
         assert st["stage"][w] == ow["stage"] and st["frozen"][w] == ow["frozen"], w
         assert st["lnf"][w] == ow["lnf"], w
+        assert phase[w] == ow["phase"], w
+        assert np.array_equal(sm[w], ow["stage_merge"]), w
         assert np.array_equal(ctx.get_visited(instance, w), ow["U"]), w
+        for k in range(g["m"]):
+            slot = w * g["m"] + k
+            assert np.array_equal(ctx.get_piece(instance, slot).view(np.uint64),
+                                  sim.piece(slot).view(np.uint64)), (w, k)
     t, r, a = ctx.get_exchange_stats(instance)
     ot, orr, oa = sim.exchange_stats()
     assert np.array_equal(t, ot) and np.array_equal(r, orr) and np.array_equal(a, oa)

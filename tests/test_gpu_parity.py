@@ -37,6 +37,11 @@ SMALL = {
                                 flips=500, seed=3, precision=WL.FP32C),
     "potts_q10_L8_fp32c": WL.config(WL.POTTS, 8, q=10, n_windows=4, walkers_per_window=4,
                                     flips=1000, seed=4, precision=WL.FP32C),
+    "ising_L8_h4_m2_1t": WL.config(WL.ISING, 8, n_windows=4, walkers_per_window=2, lnf_final=1e-4,
+                                   flips=500, seed=3, schedule=WL.ONE_OVER_T),
+    "potts_q3_L6_h3_m3_1t_fp32c": WL.config(WL.POTTS, 6, q=3, n_windows=3, walkers_per_window=3,
+                                            lnf_final=1e-4, flips=400, seed=6,
+                                            precision=WL.FP32C, schedule=WL.ONE_OVER_T),
 }
 
 
@@ -58,7 +63,8 @@ def test_initial_state_and_segments_match(name):
         compare_state(ctx, 0, sim)
 
 
-@pytest.mark.parametrize("name", ["ising_L8_h4_m2", "potts_q2_L8_h3_m2", "ising_L8_fp32c"])
+@pytest.mark.parametrize("name", ["ising_L8_h4_m2", "potts_q2_L8_h3_m2", "ising_L8_fp32c",
+                                  "ising_L8_h4_m2_1t", "potts_q3_L6_h3_m3_1t_fp32c"])
 def test_full_run_to_convergence_matches(name):
     cfg = SMALL[name]
     ctx = gpu_context([cfg])
@@ -80,6 +86,24 @@ def test_full_run_to_convergence_matches(name):
     fin = np.isfinite(nrm_o)
     assert np.array_equal(np.isfinite(nrm_g), fin)
     assert np.max(np.abs(nrm_g[fin] - nrm_o[fin])) < 1e-12
+    # jackknife over the frozen pieces (compared bitwise by compare_state):
+    # the leave-one-out joins share the normalisation's platform exp/log
+    mean_g, err_g = ctx.jackknife(0)
+    mean_o, err_o = sim.jackknife()
+    fin = np.isfinite(mean_o)
+    assert np.array_equal(np.isfinite(mean_g), fin)
+    assert np.max(np.abs(mean_g[fin] - mean_o[fin])) < 1e-12
+    np.testing.assert_allclose(err_g, err_o, rtol=1e-8, atol=1e-12)
+
+
+def test_jackknife_rejects_unfinished_runs_and_single_walkers():
+    from paper_1402_2328_amd import rewl
+    ctx = gpu_context([SMALL["ising_L8_h4_m2"], SMALL["ising_L12_h1_m1"]])
+    ctx.run_cycles(2, 500)
+    for inst in (0, 1):
+        with pytest.raises(rewl.RewlError) as e:
+            ctx.jackknife(inst)
+        assert e.value.code == -6
 
 
 def test_instances_in_a_batch_match_standalone_oracles():
