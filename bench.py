@@ -56,7 +56,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--replicas", type=int, default=1024, help="instances of the L=32 configuration")
+    ap.add_argument("--replicas", type=int, default=None,
+                    help="instances (default: 1024 for the throughput run, 8 for --converge, "
+                         "32 per h for --speedup)")
     ap.add_argument("--flips", type=int, default=10000)
     ap.add_argument("--precision", choices=["fp64", "fp32c"], default="fp64")
     ap.add_argument("--page-bins", type=int, default=0,
@@ -67,6 +69,11 @@ def parse():
     ap.add_argument("--config", choices=["cfg1", "cfg2", "cfg3", "cfg34"], default="cfg2")
     ap.add_argument("--max-minutes", type=float, default=50.0)
     ap.add_argument("--schedule", choices=["halving", "1t"], default="halving")
+    ap.add_argument("--speedup", action="store_true")
+    ap.add_argument("--L", type=int, default=32, help="lattice size (--speedup)")
+    ap.add_argument("--hs", default="1,2,4,8,16,32", help="window counts (--speedup)")
+    ap.add_argument("--walkers", type=int, default=1, help="walkers per window (--speedup)")
+    ap.add_argument("--alpha", type=float, default=2.0, help="cost exponent of the balanced split")
     ap.add_argument("--lnf-final", type=float, default=0.0,
                     help="override ln f_final of the configuration (--converge)")
     ap.add_argument("--save", default="", help="npz for ln g and jackknife errors (--converge)")
@@ -218,19 +225,111 @@ def converge(a):
     return out
 
 
+def speedup(a):
+    """Speed-up s_o(h, m) = N_single / N_o(h, m) (Eq. for the speed-up in
+    Sec. 4): N is the number of MC steps per walker the slowest window needs
+    to finish its first WL iteration.  Ising L x L (default 32), m walkers
+    per window, overlap 75 %, exchange every F flips.  Every h runs as R
+    independent instances in one batched context; N(h) is their median.
+    Then the run-time balanced split (Fig. 1b) is planned per h from the
+    equal-split runs (rewl_balanced_windows on the mean per-window first
+    iteration steps) and measured on R other seeds; a third pass re-plans
+    from both runs' data."""
+    import torch
+    from paper_1402_2328_amd import rewl
+    from paper_1402_2328_amd import workloads as WL
+    hs = [int(x) for x in a.hs.split(",")]
+    R, F, m = a.replicas, a.flips, a.walkers
+    base = WL.config(WL.ISING, a.L, n_windows=1, walkers_per_window=m, lnf_final=0.5, flips=F)
+
+    def measure(tag, split, seed0):
+        cfgs, windows = [], []
+        for h in split:
+            for r in range(R):
+                cfgs.append(dict(base, n_windows=h, seed=seed0 + r))
+                windows.append(split[h])
+        explicit = windows[0] is not None
+        assert all((w is not None) == explicit for w in windows)
+        ctx = rewl.Context([WL.rewl_params_of(c) for c in cfgs], windows=windows if explicit else None)
+        ctx.autotune(F)
+        t0 = time.perf_counter()
+        done_at, cycles, wall = run_to_convergence(ctx, len(cfgs), F, a.max_minutes * 60, tag)
+        torch.cuda.synchronize()
+        res = {}
+        i = 0
+        for h in split:
+            steps, per_window = [], []
+            for r in range(R):
+                st = ctx.status(i)
+                _, sm = ctx.get_schedule(i)
+                if st["done"]:
+                    steps.append((st["done_merge"] + 1) * F)
+                    per_window.append((sm[:, 0] + 1) * F)
+                i += 1
+            g = ctx.geometry[i - 1]
+            res[h] = {"N_median": float(np.median(steps)) if steps else None, "finished": len(steps),
+                      "per_window_mean": np.mean(np.array(per_window, float), axis=0) if per_window else None,
+                      "lo": g["lo"].copy(), "hi": g["hi"].copy(), "nbins": g["nbins"]}
+        ctx.close()
+        return res, time.perf_counter() - t0
+
+    eq, t_eq = measure("equal", {h: None for h in hs}, 1)
+    N1 = eq[hs[0]]["N_median"] if hs[0] == 1 else None
+
+    def plan(runs, h):
+        lo = np.concatenate([r[h]["lo"] for r in runs])
+        hi = np.concatenate([r[h]["hi"] for r in runs])
+        S = np.concatenate([r[h]["per_window_mean"] for r in runs])
+        return rewl.balanced_windows(runs[0][h]["nbins"], h, lo, hi, S, alpha=a.alpha)
+
+    multi = [h for h in hs if h > 1]
+    bal, t_bal = measure("balanced", {h: plan([eq], h) for h in multi}, 1 + R)
+    ref, t_ref = measure("balanced_refined", {h: plan([eq, bal], h) for h in multi}, 1 + 2 * R)
+
+    def summary(res):
+        out = {}
+        for h, r in res.items():
+            s_ = N1 / r["N_median"] if (N1 and r["N_median"]) else None
+            out[str(h)] = {"N_slowest_median": r["N_median"], "speedup": s_, "finished": r["finished"],
+                           "windows_lo": [int(x) for x in r["lo"]]}
+        pts = [(h, v["speedup"]) for h, v in ((int(k), v) for k, v in out.items()) if v["speedup"]]
+        if N1:
+            pts = [(1, 1.0)] + [p for p in pts if p[0] != 1]
+        slope = None
+        if len(pts) >= 2:
+            x = np.array([p[0] for p in pts], float)
+            y = np.array([p[1] for p in pts], float)
+            slope = float(np.polyfit(x, y, 1)[0])
+        return out, slope
+
+    out = {"metric": "speed-up s(h) = N_single / N_slowest(h), first WL iteration",
+           "config": {"workload": f"2D Ising L={a.L}, m={m} walkers/window, overlap 75%, "
+                                  f"F={F} flips per exchange, flatness 0.8, {R} instances per h",
+                      "hs": hs, "alpha": a.alpha}}
+    for name, res, t in (("equal", eq, t_eq), ("balanced", bal, t_bal), ("balanced_refined", ref, t_ref)):
+        per_h, slope = summary(res)
+        out[name] = {"per_h": per_h, "slope": slope, "wall_s": t}
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}): this build measures the "
-              "single-GPU hot path; multi-GPU REWL is a design note", file=sys.stderr)
+        print(f"bench.py measures the single-GPU path only (got --gpus {a.gpus}); REWL across "
+              "several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1402_2328_amd import rewl
     from paper_1402_2328_amd import workloads as WL
 
     torch.cuda.set_device(0)
+    if a.replicas is None:
+        a.replicas = 8 if a.converge else (32 if a.speedup else 1024)
     if a.converge:
         print(json.dumps(converge(a)), flush=True)
+        return
+    if a.speedup:
+        print(json.dumps(speedup(a)), flush=True)
         return
     if a.copy_reference:
         x = torch.empty(128 * 2 ** 20, dtype=torch.float32, device="cuda")

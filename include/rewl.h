@@ -244,6 +244,26 @@ int rewl_thermo(rewl_ctx* ctx, int32_t instance, const double* T, int32_t nT,
 int rewl_checkpoint(rewl_ctx* ctx, void* host_buf, size_t cap, size_t* used);
 int rewl_restore(rewl_ctx* ctx, const void* host_buf, size_t n);
 
+/* Host only (no device, no context).  Run-time balanced split (Fig. 1b):
+ * h window edges over bins 0..nbins-1 such that every window should finish
+ * its first WL iteration after about the same number of MC steps, from a
+ * pre-run with pre_h windows [pre_lo[v], pre_hi[v]] whose first iteration
+ * took pre_steps[v] MC steps per walker (e.g. (stage_merge[v][0] + 1) x
+ * flips_per_exchange from rewl_get_schedule, averaged over instances).
+ * Model: a window that took S steps has cost width S^(1/alpha) (alpha = 2
+ * for a diffusive walk), spread evenly over its bins; a bin's cost density
+ * is the mean over the pre-run windows containing it; the new windows are
+ * the equal split with overlap num/den done in the cumulative-cost
+ * coordinate of the bin centres, edges at the nearest bin centre (ties to
+ * the higher bin); then every window is widened to >= 5 bins and every
+ * neighbour overlap to >= 5 bins, keeping edges strictly increasing.
+ * lo, hi: h entries each, usable as win_lo / win_hi of rewl_init.
+ * Errors: INVAL (bad input, a bin no pre-run window covers, or h too large
+ * for nbins). */
+int rewl_balanced_windows(int32_t nbins, int32_t h, int32_t overlap_num, int32_t overlap_den,
+                          int32_t pre_h, const int32_t* pre_lo, const int32_t* pre_hi,
+                          const double* pre_steps, double alpha, int32_t* lo, int32_t* hi);
+
 /* Frees the host context (the caller frees the workspace). */
 int rewl_destroy(rewl_ctx* ctx);
 

@@ -17,7 +17,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librewl.so")
-SOURCES = ["rewl_sweep.hip", "rewl_kernels.hip", "rewl_api.cpp"]
+SOURCES = ["rewl_sweep.hip", "rewl_kernels.hip", "rewl_api.cpp", "rewl_plan.cpp"]
 ARCH = os.environ.get("REWL_OFFLOAD_ARCH", "gfx950")
 
 

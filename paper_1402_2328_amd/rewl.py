@@ -53,7 +53,7 @@ EXPORTS = ["rewl_workspace_bytes", "rewl_init", "rewl_run_sweeps", "rewl_set_lau
            "rewl_get_lng", "rewl_get_geometry", "rewl_get_walker", "rewl_get_walker_f32",
            "rewl_get_visited", "rewl_get_exchange_stats", "rewl_thermo", "rewl_checkpoint",
            "rewl_restore", "rewl_destroy", "rewl_strerror", "rewl_get_schedule",
-           "rewl_get_piece", "rewl_jackknife"]
+           "rewl_get_piece", "rewl_jackknife", "rewl_balanced_windows"]
 
 
 def lib():
@@ -86,6 +86,7 @@ def lib():
     L.rewl_get_schedule.argtypes = [P, I32, P, P]
     L.rewl_get_piece.argtypes = [P, I32, I32, P]
     L.rewl_jackknife.argtypes = [P, I32, P, P, I32, C.POINTER(I32)]
+    L.rewl_balanced_windows.argtypes = [I32, I32, I32, I32, I32, P, P, P, C.c_double, P, P]
     L.rewl_checkpoint.argtypes = [P, P, SZ, C.POINTER(SZ)]
     L.rewl_restore.argtypes = [P, P, SZ]
     L.rewl_destroy.argtypes = [P]
@@ -110,6 +111,21 @@ def make_params(model=ISING, L=8, q=2, n_windows=1, overlap=(3, 4), walkers_per_
     return rewl_params(model, L, q, n_windows, overlap[0], overlap[1], walkers_per_window,
                        flat[0], flat[1], precision, lnf_init, lnf_final, flips_per_exchange, seed,
                        schedule, 0)
+
+
+def balanced_windows(nbins, h, pre_lo, pre_hi, pre_steps, overlap=(3, 4), alpha=2.0):
+    """Run-time balanced split (rewl_balanced_windows); returns (lo, hi)."""
+    pl = np.ascontiguousarray(pre_lo, dtype=np.int32)
+    ph = np.ascontiguousarray(pre_hi, dtype=np.int32)
+    ps = np.ascontiguousarray(pre_steps, dtype=np.float64)
+    if not (len(pl) == len(ph) == len(ps)):
+        raise ValueError("pre-run arrays differ in length")
+    lo = np.zeros(h, np.int32)
+    hi = np.zeros(h, np.int32)
+    _check(lib().rewl_balanced_windows(int(nbins), int(h), int(overlap[0]), int(overlap[1]),
+                                       len(pl), _p(pl), _p(ph), _p(ps), float(alpha), _p(lo),
+                                       _p(hi)), "rewl_balanced_windows")
+    return lo, hi
 
 
 def _window_arrays(windows):

@@ -265,3 +265,36 @@ def test_batched_mix_sampled():
         for _ in range(cycles):
             oracle_cycle(sim, F)
         compare_state(ctx, i, sim)
+
+
+def test_balanced_split_pipeline_matches_oracle():
+    """Equal-split pre-run (first WL iteration only) -> per-window first
+    iteration steps from rewl_get_schedule -> rewl_balanced_windows -> run on
+    the balanced split; every step against the oracle."""
+    from oracle.balance import balanced_windows as oracle_balanced
+    from paper_1402_2328_amd import rewl
+    F, h = 1000, 8
+    cfgs = [WL.config(WL.ISING, 16, n_windows=h, walkers_per_window=1, lnf_final=0.5, flips=F,
+                      seed=s) for s in (1, 2, 3, 4)]
+    ctx = gpu_context(cfgs)
+    ctx.run_to_convergence(F, cycles_per_check=100)
+    steps = []
+    for i, c in enumerate(cfgs):
+        sim = oracle_sim(c, instance=i)
+        sim.run(10 ** 6)
+        compare_state(ctx, i, sim)
+        _, sm = ctx.get_schedule(i)
+        steps.append((sm[:, 0] + 1) * F)
+    g = ctx.geometry[0]
+    mean = np.mean(np.array(steps, float), axis=0)
+    lo, hi = rewl.balanced_windows(g["nbins"], h, g["lo"], g["hi"], mean)
+    olo, ohi = oracle_balanced(g["nbins"], h, (3, 4), list(g["lo"]), list(g["hi"]), list(mean))
+    assert list(lo) == olo and list(hi) == ohi
+    cfg2 = [dict(c, seed=c["seed"] + 4) for c in cfgs]
+    windows = [(lo, hi)] * len(cfg2)
+    ctx2 = gpu_context(cfg2, windows=windows)
+    ctx2.run_to_convergence(F, cycles_per_check=100)
+    for i, c in enumerate(cfg2):
+        sim = oracle_sim(c, instance=i, windows=(lo, hi))
+        sim.run(10 ** 6)
+        compare_state(ctx2, i, sim)
