@@ -121,22 +121,23 @@ int rewl_run_sweeps(rewl_ctx* ctx, int64_t flips);
 
 /* Launch shape of the sweep.  Walkers are grouped by kernel class:
  * 0 = Ising L <= 32, 1 = Ising 32 < L <= 64, 2 = Potts.  For class cls (-1:
- * all classes) keep page_bins ln g / H bins of each walker's window in LDS
- * (the rest stays in device memory; the page follows the walker) and put
+ * all classes) keep page_bins ln g bins of each walker's window in LDS (the
+ * rest stays in device memory; the page follows the walker) and put
  * walkers_per_group walkers in each 64-lane workgroup; 0 picks the default
  * (the largest page that lets four workgroups share a compute unit).
- * Results do not depend on the shape, only speed does.  out: NULL or 12
- * entries, per class {page_bins, walkers_per_group, LDS bytes per
- * workgroup, workgroups}.  Synchronises.  Errors: INVAL (shape does not fit
- * in LDS), HIP. */
+ * page_bins is rounded up to a power of two, at least 16 (32 for a class
+ * with q >= 3 Potts instances) and at most the power of two that holds the
+ * class's largest window.  Results do not depend on the shape, only speed
+ * does.  out: NULL or 12 entries, per class {page_bins, walkers_per_group,
+ * LDS bytes per workgroup, workgroups}.  Synchronises.  Errors: INVAL
+ * (shape does not fit in LDS), HIP. */
 int rewl_set_launch(rewl_ctx* ctx, int32_t cls, int32_t page_bins, int32_t walkers_per_group,
                     int32_t* out);
 
 /* Measures `repeats` sweeps of `flips` attempts for each candidate page
- * size (one per possible number of workgroups per compute unit) of every
- * class and keeps the fastest.  The simulation state is saved to host
- * memory first and restored afterwards, so tuning changes nothing but the
- * launch shape.  out: as for rewl_set_launch.  Synchronises.
+ * size (every allowed power of two) of every class and keeps the fastest.
+ * The simulation state is saved to host memory first and restored
+ * afterwards, so tuning changes nothing but the launch shape.  out: as for rewl_set_launch.  Synchronises.
  * Errors: INVAL, HIP. */
 int rewl_autotune(rewl_ctx* ctx, int64_t flips, int32_t repeats, int32_t* out);
 

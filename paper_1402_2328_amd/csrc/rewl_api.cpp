@@ -210,11 +210,12 @@ int build_layout(const rewl_params* params, int32_t n, const int32_t* wlo, const
 }
 
 // Sweep launch plan, per kernel class: walkers per workgroup (G, one
-// wavefront), ln g page rows (P), LDS bytes and the class's slice of the
-// workgroup table.  Per lane a class needs 4 * lat_words + 12 * P bytes of
-// LDS.  By default P is the largest page that still lets T = 4 (else 3, 2,
-// 1) full workgroups share a compute unit, as long as that page holds
-// min(nb_max, 32) bins.
+// wavefront), ln g page slots (P, a power of two), LDS bytes and the class's
+// slice of the workgroup table.  Per lane a class needs 4 * lat_words +
+// 12 * P bytes of LDS.  The page must hold bin +- 2D (D = 4 for q >= 3
+// Potts, else 2), so P >= 32 or 16, unless the largest window fits whole
+// (P = the power of two that holds it).  By default P is the largest page
+// that still lets T = 4 (else 3, 2, 1) full workgroups share a compute unit.
 struct ClassPlan {
   int32_t G = 0, P = 0, count = 0, offset = 0;
   size_t lds_bytes = 0;
@@ -226,25 +227,38 @@ struct LaunchPlan {
 
 int class_of(const InstDesc& I) { return I.model == REWL_POTTS ? 2 : (I.L <= 32 ? 0 : 1); }
 
+int pow2_ceil(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// Smallest and largest useful page of a class.
+void page_range(const Layout& Lo, int cls, int& pmin, int& pmax) {
+  pmax = pow2_ceil(Lo.nb_max[cls]);
+  pmin = std::min(Lo.potts3[cls] ? 32 : 16, pmax);
+}
+
 int plan_class(const Layout& Lo, int cls, int lds_budget, int page_req, int g_req, ClassPlan& cp) {
   cp = ClassPlan();
   if (Lo.walkers[cls] == 0) return REWL_OK;
   const int lat = 4 * Lo.lat_words[cls];
-  const int nbm = Lo.nb_max[cls];
+  int pmin, pmax;
+  page_range(Lo, cls, pmin, pmax);
   int P = 0, G = kSweepWave;
   if (page_req > 0) {
-    P = std::min(page_req, nbm);
+    P = std::min(std::max(pow2_ceil(page_req), pmin), pmax);
   } else {
-    const int want = std::min(nbm, 32);
     for (int T = 4; T >= 1 && P == 0; --T) {
-      const int p = (lds_budget / (kSweepWave * T) - lat) / 12;
-      if (p >= want) P = std::min(p, nbm);
+      for (int p = pmax; p >= pmin; p >>= 1) {
+        if ((size_t)kSweepWave * T * (lat + 12 * p) <= (size_t)lds_budget) {
+          P = p;
+          break;
+        }
+      }
     }
-    if (P == 0) P = want;
+    if (P == 0) P = pmin;
   }
-  // the page ring must hold bin +- 2D (D = 4 for q >= 3 Potts, else 2)
-  const int pmin = Lo.potts3[cls] ? 17 : 9;
-  if (P < pmin && P < nbm) P = std::min(pmin, nbm);
   if (g_req > 0) G = std::min(g_req, kSweepWave);
   G = std::min(G, lds_budget / (lat + 12 * P));
   if (G < 1) return REWL_E_INVAL;
@@ -534,14 +548,10 @@ int rewl_autotune(rewl_ctx* c, int64_t flips, int32_t repeats, int32_t* out) {
   LaunchPlan best = c->plan;
   for (int cls = 0; cls < 3 && !rc; ++cls) {
     if (L.walkers[cls] == 0) continue;
-    const int lat = 4 * L.lat_words[cls];
     std::vector<int> cands;
-    for (int T = 1; T <= 12; ++T) {
-      int p = (budget / (kSweepWave * T) - lat) / 12;
-      p = std::min(p, L.nb_max[cls]);
-      if (p < (L.potts3[cls] ? 17 : 9) && p < L.nb_max[cls]) continue;
-      if (std::find(cands.begin(), cands.end(), p) == cands.end()) cands.push_back(p);
-    }
+    int pmin, pmax;
+    page_range(L, cls, pmin, pmax);
+    for (int p = pmin; p <= pmax; p <<= 1) cands.push_back(p);
     float best_ms = -1.0f;
     for (int p : cands) {
       LaunchPlan pl = best;

@@ -7,6 +7,12 @@
 
 namespace rewl {
 
+// x ^ y ^ z in one instruction (gfx950 three-input bitwise op, truth table
+// 0x96).
+__device__ __forceinline__ uint32_t xor3(uint32_t x, uint32_t y, uint32_t z) {
+  return __builtin_amdgcn_bitop3_b32(x, y, z, 0x96);
+}
+
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds; each round
 // takes the 64-bit products of counter words 0 and 2 with two fixed
 // multipliers, xors their high halves with words 1, 3 and the round key, and
@@ -20,8 +26,8 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
     }
     const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
-    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1,
-                   (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+    c = make_uint4(xor3((uint32_t)(p1 >> 32), c.y, k0), (uint32_t)p1,
+                   xor3((uint32_t)(p0 >> 32), c.w, k1), (uint32_t)p0);
   }
   return c;
 }
@@ -37,38 +43,58 @@ __device__ __forceinline__ uint4 philox_rounds(uint4 c, uint32_t k0, uint32_t k1
     const uint32_t kr1 = k1 + (uint32_t)r * 0xBB67AE85u;
     const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
-    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ kr0, (uint32_t)p1,
-                   (uint32_t)(p0 >> 32) ^ c.w ^ kr1, (uint32_t)p0);
+    c = make_uint4(xor3((uint32_t)(p1 >> 32), c.y, kr0), (uint32_t)p1,
+                   xor3((uint32_t)(p0 >> 32), c.w, kr1), (uint32_t)p0);
   }
   return c;
+}
+
+// Fused multiply-add with all three operands in vector registers.  Written
+// as the instruction itself because the compiler otherwise turns a Horner
+// step with a loop-invariant coefficient into the accumulating form plus a
+// register copy of the coefficient; the arithmetic is the same single
+// rounding as fma().
+__device__ __forceinline__ double fma_vvv(double a, double b, double c) {
+  double d;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+  return d;
 }
 
 // exp(x) for x in [-40, 0): x = n ln2 + r with n = rint(x / ln2) and r from a
 // two-part split of ln2 (Cody and Waite); exp(r) by its degree-13 Taylor
 // polynomial in Horner form with fused multiply-adds; result 2^n exp(r).
-__device__ __forceinline__ double exp_det(double x) {
+// exp_det_parts returns p = exp(r) and n, so that callers can fold a further
+// power of two into the final scaling.
+__device__ __forceinline__ double exp_det_parts(double x, int& n_out) {
   const double n = rint(x * 0x1.71547652b82fep+0);
   double r = fma(-n, 0x1.62e42feep-1, x);
   r = fma(-n, 0x1.a39ef35793c76p-33, r);
   double p = 1.0 / 6227020800.0;
-  p = fma(p, r, 1.0 / 479001600.0);
-  p = fma(p, r, 1.0 / 39916800.0);
-  p = fma(p, r, 1.0 / 3628800.0);
-  p = fma(p, r, 1.0 / 362880.0);
-  p = fma(p, r, 1.0 / 40320.0);
-  p = fma(p, r, 1.0 / 5040.0);
-  p = fma(p, r, 1.0 / 720.0);
-  p = fma(p, r, 1.0 / 120.0);
-  p = fma(p, r, 1.0 / 24.0);
-  p = fma(p, r, 1.0 / 6.0);
+  p = fma_vvv(p, r, 1.0 / 479001600.0);
+  p = fma_vvv(p, r, 1.0 / 39916800.0);
+  p = fma_vvv(p, r, 1.0 / 3628800.0);
+  p = fma_vvv(p, r, 1.0 / 362880.0);
+  p = fma_vvv(p, r, 1.0 / 40320.0);
+  p = fma_vvv(p, r, 1.0 / 5040.0);
+  p = fma_vvv(p, r, 1.0 / 720.0);
+  p = fma_vvv(p, r, 1.0 / 120.0);
+  p = fma_vvv(p, r, 1.0 / 24.0);
+  p = fma_vvv(p, r, 1.0 / 6.0);
   p = fma(p, r, 0.5);
   p = fma(p, r, 1.0);
   p = fma(p, r, 1.0);
-  return ldexp(p, (int)n);
+  n_out = (int)n;
+  return p;
+}
+
+__device__ __forceinline__ double exp_det(double x) {
+  int n;
+  const double p = exp_det_parts(x, n);
+  return ldexp(p, n);
 }
 
 // Single-precision counterpart for x in [-17, 0): degree-8 Taylor polynomial.
-__device__ __forceinline__ float expf_det(float x) {
+__device__ __forceinline__ float expf_det_parts(float x, int& n_out) {
   const float n = rintf(x * 0x1.715476p+0f);
   float r = fmaf(-n, 0x1.62e000p-1f, x);
   r = fmaf(-n, 0x1.0bfbe8p-15f, r);
@@ -81,7 +107,14 @@ __device__ __forceinline__ float expf_det(float x) {
   p = fmaf(p, r, 0.5f);
   p = fmaf(p, r, 1.0f);
   p = fmaf(p, r, 1.0f);
-  return ldexpf(p, (int)n);
+  n_out = (int)n;
+  return p;
+}
+
+__device__ __forceinline__ float expf_det(float x) {
+  int n;
+  const float p = expf_det_parts(x, n);
+  return ldexpf(p, n);
 }
 
 // 53-bit uniform from two Philox words.
@@ -97,14 +130,20 @@ __device__ __forceinline__ bool accept64(uint64_t u, double delta) {
   return (double)u * 0x1p-53 < exp_det(delta);
 }
 
-// The same decision without branches: exp_det is evaluated for every lane
-// (its argument clamped into [-40, 0]) and used only where delta lies in
-// [-40, 0), so the outcome is bit-identical to accept64.
-__device__ __forceinline__ bool accept64_flat(uint64_t u, double delta) {
+// The same decision without branches, from the two Philox words hi, lo of
+// the uniform.  With x = delta clamped into [-40, 0]:
+//   delta >= 0:   x = 0 and exp_det(0) = 1 exactly, and u * 2^-53 < 1 always;
+//   delta < -40:  x = -40 and 0 < exp_det(-40) < 2^-53, so u * 2^-53 < it
+//                 iff u == 0;
+// so the single comparison u * 2^-53 < exp_det(x) is accept64.  Both sides
+// are then scaled by 2^53 (exact): u = hi * 2^21 + (lo >> 11) is formed
+// exactly in FP64 and compared with 2^(n+53) p.
+__device__ __forceinline__ bool accept64_flat(uint32_t hi, uint32_t lo, double delta) {
   const double x = fmin(fmax(delta, -40.0), 0.0);
-  const double e = exp_det(x);
-  const bool mid = (double)u * 0x1p-53 < e;
-  return (delta >= 0.0) || (delta < -40.0 ? (u == 0) : mid);
+  int n;
+  const double p = exp_det_parts(x, n);
+  const double u = fma((double)hi, 0x1p21, (double)(lo >> 11));
+  return u < ldexp(p, n + 53);
 }
 
 // Same with a 24-bit uniform (exp(-17) < 2^-24).
@@ -114,11 +153,13 @@ __device__ __forceinline__ bool accept32(uint32_t u, float delta) {
   return (float)u * 0x1p-24f < expf_det(delta);
 }
 
+// Branch-free accept32 (exp(-17) < 2^-24 and expf_det(0) = 1, as above):
+// the comparison u < 2^(n+24) p on the 24-bit uniform u.
 __device__ __forceinline__ bool accept32_flat(uint32_t u, float delta) {
   const float x = fminf(fmaxf(delta, -17.0f), 0.0f);
-  const float e = expf_det(x);
-  const bool mid = (float)u * 0x1p-24f < e;
-  return (delta >= 0.0f) || (delta < -17.0f ? (u == 0) : mid);
+  int n;
+  const float p = expf_det_parts(x, n);
+  return (float)u < ldexpf(p, n + 24);
 }
 
 // ---- two-float arithmetic (Knuth's TwoSum, Dekker's FastTwoSum) ----

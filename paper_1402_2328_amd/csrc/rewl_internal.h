@@ -16,7 +16,6 @@ constexpr int kMaxWalkersPerWindow = 64;
 constexpr int kMaxL = 64;
 constexpr int kSweepWave = 64;    // one wavefront per sweep workgroup
 constexpr int kMaxTemps = 16384;  // rewl_thermo temperatures per call
-constexpr int kMinPageBins = 16;  // smallest ln g page the launch planner picks
 
 enum Model : int32_t { kIsing = 0, kPotts = 1 };
 enum Prec : int32_t { kFP64 = 0, kFP32C = 1 };

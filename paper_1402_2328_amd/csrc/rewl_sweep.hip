@@ -4,12 +4,17 @@
 // instance.  For the duration of a launch every walker keeps in LDS
 //   * its lattice: Ising spins as bit rows (one 32-bit word per row for
 //     L <= 32, two for L <= 64), Potts spins as bytes;
-//   * a page of P consecutive bins of its ln g and H window, kept as a ring.
-//     Walkers move at most D bins per attempt (D = 2 for Ising and q = 2
-//     Potts, 4 for q >= 3 Potts); the page always covers [bin - 2D,
-//     bin + 2D] inside the window and follows the walker by at most D bins
-//     per move through device memory, with the fetched bins committed one
-//     attempt later.  Windows of at most P bins live in LDS entirely.
+//   * a page of PG = 2^k bins of its ln g window, direct-mapped (bin b lives
+//     in slot b mod PG), with the histogram increments H gathered since the
+//     launch began.  Walkers move at most D bins per attempt (D = 2 for
+//     Ising and q = 2 Potts, 4 for q >= 3 Potts); the page always covers
+//     [bin - 2D, bin + 2D] inside the window and follows the walker by at
+//     most D bins per move: the bin that leaves is written back (ln g
+//     stored, its H increments added to the histogram in device memory) and
+//     the bin that enters shares its slot; the entering ln g is loaded into
+//     registers and committed one attempt later, since it cannot be reached
+//     before then, so the wave never waits for device memory inside the
+//     loop.  Windows of at most PG bins live in LDS entirely.
 // LDS is interleaved by lane: element e of lane l sits at e * S + l (S =
 // lanes per workgroup), so the 32-bit words that one instruction touches
 // across the wavefront fall into consecutive banks.  Random numbers come
@@ -28,6 +33,13 @@ namespace rewl {
 // below it nor merge slices across it.
 #define REWL_PIN4(v) asm volatile("" : "+v"((v).x), "+v"((v).y), "+v"((v).z), "+v"((v).w))
 
+// Element at a 32-bit byte offset from a wave-uniform base pointer (the
+// scalar-base addressing mode of global memory instructions).
+template <typename T>
+__device__ __forceinline__ T* at_off(T* base, uint32_t byte_off) {
+  return reinterpret_cast<T*>(reinterpret_cast<unsigned char*>(base) + byte_off);
+}
+
 template <int MODEL, int PREC, int ROWW>
 __global__ __launch_bounds__(kSweepWave) void k_sweep(DevPtrs P, SweepShape sh, int64_t flips) {
   extern __shared__ __align__(16) unsigned char lds[];
@@ -39,7 +51,8 @@ __global__ __launch_bounds__(kSweepWave) void k_sweep(DevPtrs P, SweepShape sh, 
 
   const int S = sh.stride;
   const int NWL = sh.nw;   // lattice words per lane
-  const int PG = sh.page;  // page rows per lane
+  const int PG = sh.page;  // page slots per lane, a power of two
+  const int PM = PG - 1;
   uint32_t* lat = reinterpret_cast<uint32_t*>(lds);                           // [NWL][S]
   unsigned char* latb = lds;                                                   // byte view (Potts)
   unsigned char* pg = lds + (size_t)4 * NWL * S;
@@ -53,6 +66,7 @@ __global__ __launch_bounds__(kSweepWave) void k_sweep(DevPtrs P, SweepShape sh, 
   const uint32_t k0 = Ig.key0, k1 = Ig.key1;
   const uint32_t tagw = kTagMC | ((uint32_t)Ig.inst << 8);
   const int D = (MODEL == kPotts && bshift == 0) ? 4 : 2;  // largest bin step of one move
+  const int M = 2 * D;
 
   const int g = wg.slot_first + lane;
   const int loc = g - Ig.slot_base;
@@ -64,8 +78,19 @@ __global__ __launch_bounds__(kSweepWave) void k_sweep(DevPtrs P, SweepShape sh, 
   const bool frozen = WS.frozen != 0;
   const double lnf = WS.lnf;
   const float lnf32 = (float)WS.lnf;
-  const int64_t gbase = W.lng_base + (int64_t)k * nb;  // global element of (walker, bin lo)
-  const int pn = nb < PG ? nb : PG;                     // page length of this walker
+
+  // The walkers of a workgroup are consecutive slots of one instance, so
+  // their ln g / H rows form one span that starts at the row of the first
+  // walker; bins are addressed by 32-bit offsets from that base.
+  const int loc0 = wg.slot_first - Ig.slot_base;
+  const int w0 = loc0 / Ig.m;
+  const WinDesc W0 = P.win[Ig.win_base + w0];
+  const int64_t gb0 = W0.lng_base + (int64_t)(loc0 - w0 * Ig.m) * W0.nb;
+  const uint32_t eoff = (uint32_t)(W.lng_base + (int64_t)k * nb - gb0) - (uint32_t)lo;  // + bin
+  double* const lngw = PREC == kFP64 ? P.lng + gb0 : nullptr;
+  float* const lhw = PREC == kFP64 ? nullptr : P.lhi + gb0;
+  float* const llw = PREC == kFP64 ? nullptr : P.llo + gb0;
+  uint32_t* const Hw = P.H + gb0;
 
   int32_t E = P.E[g];
   uint64_t att = P.att[g];
@@ -94,52 +119,46 @@ __global__ __launch_bounds__(kSweepWave) void k_sweep(DevPtrs P, SweepShape sh, 
     for (int i = 0; i < nwi; ++i) lat[i * S + lane] = src[i];
   }
 
-  // ---- page of ln g / H: a ring of pn slots over bins [pbase, pbase+pn) ----
-  // Slot of bin b: (ps + b - pbase) mod pn.  The page always covers
-  // [bin - 2D, bin + 2D] inside the window; after a move it shifts by at
-  // most D bins, writing the bins it drops back to device memory and
-  // fetching the bins it gains into registers, which are committed to LDS
-  // one attempt later (they cannot be reached before then), so the wave
-  // never waits for device memory inside the loop.
-  const int M = 2 * D;
-  int pbase = bin - (pn >> 1);
-  pbase = pbase < lo ? lo : pbase;
-  pbase = pbase > hi - pn + 1 ? hi - pn + 1 : pbase;
-  int ps = 0;
-  for (int j = 0; j < pn; ++j) {
-    const int64_t e = gbase + (pbase - lo) + j;
-    if (PREC == kFP64) {
-      plg[j * S + lane] = P.lng[e];
-    } else {
-      plh[j * S + lane] = P.lhi[e];
-      pll[j * S + lane] = P.llo[e];
-    }
-    pH[j * S + lane] = P.H[e];
+  // ---- page: bins [base, base + cnt) of the window, slot of bin b = b & PM
+  const bool paged = nb > PG;
+  int base = lo;
+  if (paged) {
+    base = bin - (PG >> 1);
+    base = base < lo ? lo : base;
+    base = base > hi - PM ? hi - PM : base;
   }
-  auto slot_of = [&](int b) {
-    const int v = ps + (b - pbase);
-    return v >= pn ? v - pn : v;
-  };
+  const int cnt = paged ? PG : nb;
+  for (int i = 0; i < cnt; ++i) {
+    const int b = base + i;
+    const int j = __mul24(b & PM, S) + lane;
+    const uint32_t e = eoff + (uint32_t)b;
+    if (PREC == kFP64) {
+      plg[j] = *at_off(lngw, e << 3);
+    } else {
+      plh[j] = *at_off(lhw, e << 2);
+      pll[j] = *at_off(llw, e << 2);
+    }
+    pH[j] = 0;
+  }
   constexpr int DMAX = (MODEL == kPotts) ? 4 : 2;
   int pend_n = 0;
-  int pend_slot[DMAX];
+  int pend_row[DMAX];
   double pend_l[DMAX];
   float pend_hi[DMAX], pend_lo[DMAX];
-  uint32_t pend_H[DMAX];
 #pragma unroll
   for (int i = 0; i < DMAX; ++i) {
-    pend_slot[i] = 0;
+    pend_row[i] = 0;
     pend_l[i] = 0.0;
     pend_hi[i] = pend_lo[i] = 0.0f;
-    pend_H[i] = 0;
   }
 
+  int jcur = __mul24(bin & PM, S) + lane;  // LDS row index of the current bin
   double lcur = 0.0;
   float hcur = 0.0f, lcur_lo = 0.0f;
-  if (PREC == kFP64) lcur = plg[(bin - pbase) * S + lane];
+  if (PREC == kFP64) lcur = plg[jcur];
   else {
-    hcur = plh[(bin - pbase) * S + lane];
-    lcur_lo = pll[(bin - pbase) * S + lane];
+    hcur = plh[jcur];
+    lcur_lo = pll[jcur];
   }
 
   const int lane4 = lane * 4;
@@ -226,7 +245,7 @@ __global__ __launch_bounds__(kSweepWave) void k_sweep(DevPtrs P, SweepShape sh, 
     }
     const int bn = bin + db;
     const bool inwin = (bn >= lo) && (bn <= hi);
-    const int jn = prow(slot_of(inwin ? bn : bin));
+    const int jn = inwin ? prow(bn & PM) : jcur;
     bool acc;
     if (PREC == kFP64) {
       const double ln = plg[jn];
@@ -234,7 +253,7 @@ __global__ __launch_bounds__(kSweepWave) void k_sweep(DevPtrs P, SweepShape sh, 
       rn = philox_rounds<4, 7>(rn, k0, k1);
       REWL_PIN4(rn);
       __builtin_amdgcn_sched_barrier(0);
-      const bool a = accept64_flat(u53(r.z, r.w), lcur - ln);
+      const bool a = accept64_flat(r.z, r.w, lcur - ln);
       rn = philox_rounds<7, 10>(rn, k0, k1);
       REWL_PIN4(rn);
       acc = inwin && a;
@@ -262,81 +281,68 @@ __global__ __launch_bounds__(kSweepWave) void k_sweep(DevPtrs P, SweepShape sh, 
       E += dE;
       bin = bn;
     }
+    jcur = acc ? jn : jcur;
     if (!frozen) {
-      const int j = prow(slot_of(bin));
       if (PREC == kFP64) {
         lcur = lcur + lnf;
-        plg[j] = lcur;
+        plg[jcur] = lcur;
       } else {
         df_add1(hcur, lcur_lo, lnf32, hcur, lcur_lo);
-        plh[j] = hcur;
-        pll[j] = lcur_lo;
+        plh[jcur] = hcur;
+        pll[jcur] = lcur_lo;
       }
-      atomicAdd(&pH[j], 1u);  // no-return LDS add: the lane owns this word
+      atomicAdd(&pH[jcur], 1u);  // no-return LDS add: the lane owns this word
     }
     // commit the bins fetched one attempt ago, then follow the walker
 #pragma unroll
     for (int i = 0; i < DMAX; ++i) {
       if (i < pend_n) {
-        const int j = prow(pend_slot[i]);
+        const int j = pend_row[i];
         if (PREC == kFP64) {
           plg[j] = pend_l[i];
         } else {
           plh[j] = pend_hi[i];
           pll[j] = pend_lo[i];
         }
-        pH[j] = pend_H[i];
+        pH[j] = 0;
       }
     }
     pend_n = 0;
-    if (pn < nb) {
-      const int top = pbase + pn - 1;
-      const int want_top = (bin + M < hi) ? bin + M : hi;
-      const int want_bot = (bin - M > lo) ? bin - M : lo;
-      const bool up = want_top > top;
-      const bool down = want_bot < pbase;
-      if (up || down) {
-        const int sh = up ? want_top - top : pbase - want_bot;  // 1..D
+    if (paged) {
+      const int top = base + PM;
+      const int up = ((bin + M < hi) ? bin + M : hi) - top;
+      const int dn = base - ((bin - M > lo) ? bin - M : lo);
+      const int shn = up > 0 ? up : (dn > 0 ? dn : 0);  // 0..D
+      if (shn > 0) {
 #pragma unroll
         for (int i = 0; i < DMAX; ++i) {
-          if (i < sh) {
-            // up: drop bin pbase+i, gain top+1+i; down: drop top-i, gain pbase-1-i
-            int es = up ? ps + i : ps + pn - 1 - i;
-            es = es >= pn ? es - pn : es;
-            const int drop = up ? pbase + i : top - i;
-            const int gain = up ? top + 1 + i : pbase - 1 - i;
-            const int j = prow(es);
+          if (i < shn) {
+            // up: bin base+i leaves, base+i+PG enters; down: top-i leaves,
+            // top-i-PG enters -- the same slot
+            const int ev = up > 0 ? base + i : top - i;
+            const uint32_t e = eoff + (uint32_t)ev;
+            const uint32_t en = up > 0 ? e + (uint32_t)PG : e - (uint32_t)PG;
+            const int j = prow(ev & PM);
             if (!frozen) {
-              const int64_t eg = gbase + (drop - lo);
               if (PREC == kFP64) {
-                P.lng[eg] = plg[j];
+                *at_off(lngw, e << 3) = plg[j];
               } else {
-                P.lhi[eg] = plh[j];
-                P.llo[eg] = pll[j];
+                *at_off(lhw, e << 2) = plh[j];
+                *at_off(llw, e << 2) = pll[j];
               }
-              P.H[eg] = pH[j];
+              atomicAdd(at_off(Hw, e << 2), pH[j]);
             }
-            const int64_t ng = gbase + (gain - lo);
             if (PREC == kFP64) {
-              pend_l[i] = P.lng[ng];
+              pend_l[i] = *at_off(lngw, en << 3);
             } else {
-              pend_hi[i] = P.lhi[ng];
-              pend_lo[i] = P.llo[ng];
+              pend_hi[i] = *at_off(lhw, en << 2);
+              pend_lo[i] = *at_off(llw, en << 2);
             }
-            pend_H[i] = P.H[ng];
-            pend_slot[i] = es;
+            pend_row[i] = j;
           }
         }
-        pend_n = sh;
-        if (up) {
-          pbase += sh;
-          ps += sh;
-          ps = ps >= pn ? ps - pn : ps;
-        } else {
-          pbase -= sh;
-          ps += pn - sh;
-          ps = ps >= pn ? ps - pn : ps;
-        }
+        base += up > 0 ? shn : -shn;
+        pend_n = shn;
       }
     }
     r = rn;
@@ -347,27 +353,29 @@ __global__ __launch_bounds__(kSweepWave) void k_sweep(DevPtrs P, SweepShape sh, 
 #pragma unroll
   for (int i = 0; i < DMAX; ++i) {
     if (i < pend_n) {
-      const int j = prow(pend_slot[i]);
+      const int j = pend_row[i];
       if (PREC == kFP64) {
         plg[j] = pend_l[i];
       } else {
         plh[j] = pend_hi[i];
         pll[j] = pend_lo[i];
       }
-      pH[j] = pend_H[i];
+      pH[j] = 0;
     }
   }
   if (!frozen) {
-    for (int j = 0; j < pn; ++j) {
-      const int64_t e = gbase + (pbase - lo) + j;
-      const int sl = prow(slot_of(pbase + j));
+    for (int i = 0; i < cnt; ++i) {
+      const int b = base + i;
+      const int j = prow(b & PM);
+      const uint32_t e = eoff + (uint32_t)b;
       if (PREC == kFP64) {
-        P.lng[e] = plg[sl];
+        *at_off(lngw, e << 3) = plg[j];
       } else {
-        P.lhi[e] = plh[sl];
-        P.llo[e] = pll[sl];
+        *at_off(lhw, e << 2) = plh[j];
+        *at_off(llw, e << 2) = pll[j];
       }
-      P.H[e] = pH[sl];
+      const uint32_t h = pH[j];
+      if (h) atomicAdd(at_off(Hw, e << 2), h);
     }
   }
   if (MODEL == kIsing) {

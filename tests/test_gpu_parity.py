@@ -195,17 +195,24 @@ def test_unreachable_window_is_reported_on_both_sides():
     assert ctx.running() == 0
 
 
-@pytest.mark.parametrize("name,page,group", [("ising_L16_h5_m4", 9, 0), ("ising_L16_h5_m4", 0, 5),
-                                             ("potts_q5_L12_h9_m7_ragged", 12, 13),
-                                             ("potts_q10_L8_h4_m4", 10, 3),
-                                             ("ising_L40_h6_m2_tworow", 17, 0),
-                                             ("potts_q10_L8_fp32c", 9, 7)])
+@pytest.mark.parametrize("name,page,group", [("ising_L16_h5_m4", 16, 0), ("ising_L16_h5_m4", 0, 5),
+                                             ("ising_L16_h5_m4", 64, 0),
+                                             ("potts_q5_L12_h9_m7_ragged", 32, 13),
+                                             ("potts_q10_L8_h4_m4", 32, 3),
+                                             ("ising_L40_h6_m2_tworow", 16, 0),
+                                             ("ising_L8_fp32c", 16, 0),
+                                             ("potts_q10_L8_fp32c", 32, 7)])
 def test_page_size_and_group_shape_do_not_change_results(name, page, group):
-    """Small ln g pages force frequent re-centring through device memory."""
+    """Pages much smaller than the windows make the page follow the walker
+    through device memory at almost every move; results must not change."""
     cfg = SMALL[name]
     ctx = gpu_context([cfg])
     plan = ctx.set_launch(page_bins=page, walkers_per_group=group)
     print(f"[parity] {name}: plan {plan}", flush=True)
+    (p,) = plan.values()
+    assert p["page_bins"] & (p["page_bins"] - 1) == 0
+    if page:
+        assert p["page_bins"] == page
     sim = oracle_sim(cfg)
     F = cfg["flips_per_exchange"]
     for seg in (3, 30):
