@@ -106,14 +106,15 @@ def cpu_baseline(flips, seconds):
 
 def traffic_from_profile(R, flips, page):
     """HBM bytes per sweep launch from the committed rocprofv3 counters, if
-    they were taken on the current kernel source and workload (else None)."""
+    they were taken on the current kernel sources and workload (else None)."""
     try:
         prof = json.load(open(PROFILE))
     except (OSError, ValueError):
         return None
-    src = open(os.path.join(ROOT, "paper_1402_2328_amd", "csrc", "rewl_sweep.hip"), "rb").read()
-    if prof.get("source_sha256") != hashlib.sha256(src).hexdigest():
-        return None
+    csrc = os.path.join(ROOT, "paper_1402_2328_amd", "csrc")
+    for key, name in (("source_sha256", "rewl_sweep.hip"), ("device_h_sha256", "rewl_device.h")):
+        if prof.get(key) != hashlib.sha256(open(os.path.join(csrc, name), "rb").read()).hexdigest():
+            return None
     if prof.get("replicas") != R or prof.get("flips") != flips or prof.get("page_bins") != page:
         return None
     return (prof["fetch_kib"] * prof["fetch_scale"] + prof["write_kib"] * prof["write_scale"]) * 1024
