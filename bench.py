@@ -13,6 +13,10 @@ Printed: one JSON line with spin-flip attempts/s, the sweep kernel's
 roofline position (kernel time from HIP events recorded on the library's
 stream) and the single-threaded CPU oracle's attempts/s on a bounded sample.
 
+--workload cfg3 (q=10 Potts L=20, filled with copies) or mix (the batched
+64-instance mix) measures the other forms; --precision fp32c the two-float
+FP32 ln g.
+
 --converge --config {cfg1,cfg2,cfg3,cfg34} [--schedule halving|1t] runs R
 copies of a configuration to ln f <= ln f_final and reports time to
 convergence and the C_V peak (Potts); cfg34 runs the q=10 Potts instances in
@@ -61,6 +65,9 @@ def parse():
                          "32 per h for --speedup)")
     ap.add_argument("--flips", type=int, default=10000)
     ap.add_argument("--precision", choices=["fp64", "fp32c"], default="fp64")
+    ap.add_argument("--workload", choices=["cfg2", "cfg3", "mix"], default="cfg2",
+                    help="throughput run: Ising L=32 (default), q=10 Potts L=20, or the "
+                         "64-instance batched mix")
     ap.add_argument("--page-bins", type=int, default=0,
                     help="fixed ln g page size for the sweep (0: autotune)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -324,8 +331,8 @@ def main():
     from paper_1402_2328_amd import workloads as WL
 
     torch.cuda.set_device(0)
-    if a.replicas is None:
-        a.replicas = 8 if a.converge else (32 if a.speedup else 1024)
+    if a.replicas is None and (a.converge or a.speedup):
+        a.replicas = 8 if a.converge else 32
     if a.converge:
         print(json.dumps(converge(a)), flush=True)
         return
@@ -341,11 +348,26 @@ def main():
         print(json.dumps({"copy_reference_bytes": 4 * x.numel(), "copies": 3, "check": float(y[0])}))
         return
     prec = WL.FP64 if a.precision == "fp64" else WL.FP32C
-    cfg = dict(WL.CFG2, precision=prec, flips_per_exchange=a.flips)
-    R = a.replicas
-    ctx = rewl.Context([WL.rewl_params_of(cfg)] * R)
+    if a.workload == "cfg2":
+        cfg = dict(WL.CFG2, precision=prec, flips_per_exchange=a.flips)
+        R = a.replicas or 1024
+        cfgs = [cfg] * R
+        name = (f"2D Ising L=32 REWL, 16 windows x 8 walkers, 75% overlap, flatness 0.8, "
+                f"F={a.flips} flips per exchange, x{R} independent instances")
+    elif a.workload == "cfg3":
+        cfg = dict(WL.CFG3, precision=prec, flips_per_exchange=a.flips)
+        R = a.replicas or WL.bench_replicas(cfg)
+        cfgs = [cfg] * R
+        name = (f"2D q=10 Potts L=20 REWL, 32 windows x 16 walkers, 75% overlap, flatness 0.8, "
+                f"F={a.flips} flips per exchange, x{R} independent instances")
+    else:
+        R = a.replicas or 1
+        cfgs = [dict(c, flips_per_exchange=a.flips) for c in WL.batched_mix(precision=prec)] * R
+        name = (f"batched mix of 64 Ising/Potts REWL instances (L 16-64, q 2-10, 8-48 windows x "
+                f"4-16 walkers), F={a.flips} flips per exchange, x{R}")
+    ctx = rewl.Context([WL.rewl_params_of(c) for c in cfgs])
     plan = ctx.set_launch(page_bins=a.page_bins) if a.page_bins > 0 else ctx.autotune(a.flips)
-    W = R * cfg["n_windows"] * cfg["walkers_per_window"]
+    W = sum(c["n_windows"] * c["walkers_per_window"] for c in cfgs)
     stream = ctx.stream
 
     def step(ev=None):
@@ -386,9 +408,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prec == WL.FP64 else "f32x2",
         "data": "synthetic (seeded Philox initial lattices)",
-        "config": {"workload": f"2D Ising L=32 REWL, 16 windows x 8 walkers, 75% overlap, "
-                               f"flatness 0.8, F={a.flips} flips per exchange, x{R} independent "
-                               f"instances", "replicas": R, "walkers": W, "flips": a.flips,
+        "config": {"workload": name, "replicas": R, "walkers": W, "flips": a.flips,
                    "precision": a.precision, "launch": plan},
         "roofline": {"bound": "alu", "achieved": achieved_valu / 1e12, "peak": PEAK_VALU / 1e12,
                      "unit": "Tlane-op/s", "frac": achieved_valu / PEAK_VALU,
@@ -401,7 +421,11 @@ def main():
         "sweep_attempts_per_s": sweep_rate,
         "stage_of_instance0": int(np.max(st["stage"])),
     }
-    if not a.no_cpu:
+    if a.workload != "cfg2" or prec != WL.FP64:
+        # the algorithmic slot count above is that of the FP64 Ising attempt
+        out["roofline"] = None
+        out["kernel_ms"] = sweep_ms
+    if not a.no_cpu and a.workload == "cfg2":
         out["cpu_baseline"] = cpu_baseline(a.flips, a.cpu_seconds)
     print(json.dumps(out), flush=True)
 

@@ -35,7 +35,11 @@
  *     owns only the host-side context object.
  *   - Streams: run/merge/exchange/init calls only enqueue work on the
  *     hipStream_t given to rewl_init (a null pointer means the legacy default
- *     stream) and return without synchronising.  rewl_status, rewl_get_*,
+ *     stream) and return without synchronising.  When a batch holds
+ *     instances of more than one sweep kernel class, the sweeps of the other
+ *     classes run on two streams the library owns, forked from that stream
+ *     and joined back to it by events, so work enqueued on the caller's
+ *     stream afterwards still sees finished sweeps.  rewl_status, rewl_get_*,
  *     rewl_thermo, rewl_checkpoint and rewl_restore synchronise that stream.
  *   - Calls on one context are not thread-safe.  Per cycle the call order is
  *     rewl_run_sweeps -> rewl_merge -> rewl_exchange.
@@ -135,7 +139,10 @@ int rewl_set_launch(rewl_ctx* ctx, int32_t cls, int32_t page_bins, int32_t walke
                     int32_t* out);
 
 /* Measures `repeats` sweeps of `flips` attempts for each candidate page
- * size (every allowed power of two) of every class and keeps the fastest.
+ * size (every allowed power of two) of every class, class by class with the
+ * other classes at their best page so far, and keeps the fastest.  Sweeps
+ * of different classes run concurrently, so every candidate is timed on
+ * the whole batch.
  * The simulation state is saved to host memory first and restored
  * afterwards, so tuning changes nothing but the launch shape.  out: as for rewl_set_launch.  Synchronises.
  * Errors: INVAL, HIP. */

@@ -311,6 +311,12 @@ struct rewl_ctx {
   unsigned char* ws = nullptr;
   size_t ws_bytes = 0;
   hipStream_t stream = nullptr;
+  // Sweeps of different kernel classes touch disjoint instances and run
+  // side by side: class k > first on side[k-1], forked from and joined
+  // back to `stream` by events (also inside a captured graph).
+  hipStream_t side[2] = {nullptr, nullptr};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[2] = {nullptr, nullptr};
   DevPtrs P{};
   hipGraphExec_t graph = nullptr;
   int64_t graph_flips = -1;
@@ -370,15 +376,56 @@ int d2h(rewl_ctx* c, T* dst, const void* src, size_t count) {
 }
 
 hipError_t enqueue_sweeps(rewl_ctx* c, int64_t flips, int only_class = -1) {
+  int active[3], n = 0;
   for (int cls = 0; cls < 3; ++cls) {
     if (only_class >= 0 && cls != only_class) continue;
-    const ClassPlan& cp = c->plan.cls[cls];
-    if (cp.count == 0) continue;
-    SweepShape sh{cp.G, c->lo.lat_words[cls], cp.P, cp.offset};
-    hipError_t e = launch_sweep_class(c->P, cls, sh, cp.count, flips, cp.lds_bytes, c->stream);
-    if (e != hipSuccess) return e;
+    if (c->plan.cls[cls].count > 0) active[n++] = cls;
   }
-  return hipSuccess;
+  const bool fork = n > 1 && c->side[0] != nullptr;
+  hipError_t e = hipSuccess;
+  if (fork) {
+    e = hipEventRecord(c->fork, c->stream);
+    for (int i = 1; i < n && e == hipSuccess; ++i) e = hipStreamWaitEvent(c->side[i - 1], c->fork, 0);
+  }
+  for (int i = 0; i < n && e == hipSuccess; ++i) {
+    const int cls = active[i];
+    const ClassPlan& cp = c->plan.cls[cls];
+    SweepShape sh{cp.G, c->lo.lat_words[cls], cp.P, cp.offset};
+    hipStream_t s = (fork && i > 0) ? c->side[i - 1] : c->stream;
+    e = launch_sweep_class(c->P, cls, sh, cp.count, flips, cp.lds_bytes, s);
+  }
+  if (fork) {
+    for (int i = 1; i < n && e == hipSuccess; ++i) {
+      e = hipEventRecord(c->join[i - 1], c->side[i - 1]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, c->join[i - 1], 0);
+    }
+  }
+  return e;
+}
+
+void destroy_side_streams(rewl_ctx* c) {
+  for (int i = 0; i < 2; ++i) {
+    if (c->side[i]) (void)hipStreamDestroy(c->side[i]);
+    if (c->join[i]) (void)hipEventDestroy(c->join[i]);
+    c->side[i] = nullptr;
+    c->join[i] = nullptr;
+  }
+  if (c->fork) (void)hipEventDestroy(c->fork);
+  c->fork = nullptr;
+}
+
+// Side streams for concurrent sweep classes, when the batch has more than one.
+hipError_t create_side_streams(rewl_ctx* c) {
+  int classes = 0;
+  for (int cls = 0; cls < 3; ++cls) classes += c->lo.walkers[cls] > 0;
+  if (classes < 2) return hipSuccess;
+  hipError_t e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
+  for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+    e = hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join[i], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) destroy_side_streams(c);
+  return e;
 }
 
 int enqueue_cycle(rewl_ctx* c, int64_t flips) {
@@ -470,7 +517,9 @@ int rewl_init(const rewl_params* params, int32_t n, const int32_t* win_lo, const
   if (e == hipSuccess) e = launch_init(c->P, c->stream);
   // host vectors above are pageable; make sure the copies finished
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) e = create_side_streams(c);
   if (e != hipSuccess) {
+    destroy_side_streams(c);
     delete c;
     return REWL_E_HIP;
   }
@@ -562,7 +611,9 @@ int rewl_autotune(rewl_ctx* c, int64_t flips, int32_t repeats, int32_t* out) {
       if (!rc) rc = hip_rc(hipMemcpyAsync(c->ws + L.o_ist, snap.data() + L.o_ist, L.total - L.o_ist,
                                           hipMemcpyHostToDevice, c->stream));
       if (!rc) rc = hip_rc(hipEventRecord(e0, c->stream));
-      for (int r = 0; r < repeats && !rc; ++r) rc = hip_rc(enqueue_sweeps(c, flips, cls));
+      // the classes run side by side, so time all of them with this
+      // candidate for `cls` and the best pages found so far for the others
+      for (int r = 0; r < repeats && !rc; ++r) rc = hip_rc(enqueue_sweeps(c, flips));
       if (!rc) rc = hip_rc(hipEventRecord(e1, c->stream));
       if (!rc) rc = sync(c);
       float ms = 0.0f;
@@ -883,6 +934,7 @@ int rewl_restore(rewl_ctx* c, const void* buf, size_t n) {
 int rewl_destroy(rewl_ctx* c) {
   if (!c) return REWL_E_INVAL;
   if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  destroy_side_streams(c);
   delete c;
   return REWL_OK;
 }
