@@ -67,6 +67,10 @@ __global__ __launch_bounds__(kSweepWave) void k_sweep(DevPtrs P, SweepShape sh, 
   const uint32_t tagw = kTagMC | ((uint32_t)Ig.inst << 8);
   const int D = (MODEL == kPotts && bshift == 0) ? 4 : 2;  // largest bin step of one move
   const int M = 2 * D;
+  // row and column of a site: shifts and masks when L is a power of two
+  const bool pow2 = (L & (L - 1)) == 0;
+  const int Lm = L - 1;
+  const int lgL = 31 - __builtin_clz((unsigned)L);
 
   const int g = wg.slot_first + lane;
   const int loc = g - Ig.slot_base;
@@ -177,12 +181,22 @@ __global__ __launch_bounds__(kSweepWave) void k_sweep(DevPtrs P, SweepShape sh, 
     const uint64_t an = att + 1;
     const uint4 cn = make_uint4((uint32_t)an, (uint32_t)(an >> 32), (uint32_t)loc, tagw);
     const int site = (int)__umulhi(r.x, (uint32_t)N);
-    const int y = (int)(((float)site + 0.5f) * invL);
-    const int x = site - __mul24(y, L);
-    const int xr = (x + 1 == L) ? 0 : x + 1;
-    const int xl = (x == 0) ? L - 1 : x - 1;
-    const int yd = (y + 1 == L) ? 0 : y + 1;
-    const int yu = (y == 0) ? L - 1 : y - 1;
+    int y, x, xr, xl, yd, yu;
+    if (pow2) {  // uniform: shifts and masks
+      y = site >> lgL;
+      x = site & Lm;
+      xr = (x + 1) & Lm;
+      xl = (x - 1) & Lm;
+      yd = (y + 1) & Lm;
+      yu = (y - 1) & Lm;
+    } else {
+      y = (int)(((float)site + 0.5f) * invL);
+      x = site - __mul24(y, L);
+      xr = (x + 1 == L) ? 0 : x + 1;
+      xl = (x == 0) ? L - 1 : x - 1;
+      yd = (y + 1 == L) ? 0 : y + 1;
+      yu = (y == 0) ? L - 1 : y - 1;
+    }
     int dE, db, nv = 0;
     int widx = 0;
     uint32_t wrow = 0;
