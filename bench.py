@@ -21,8 +21,10 @@ FP32 ln g.
 copies of a configuration to ln f <= ln f_final and reports time to
 convergence and the C_V peak (Potts); cfg34 runs the q=10 Potts instances in
 FP64 and in two-float FP32 and compares them (progress lines precede the
-JSON line).  --save keeps the normalised ln g and jackknife errors for
-scoring against exact results by tests/converge_report.py.
+JSON line).  --balanced first plans run-time balanced windows (Fig. 1b)
+from a first-iteration pre-run.  --save keeps the normalised ln g and
+jackknife errors for scoring against exact results by
+tests/converge_report.py.
 """
 import argparse
 import hashlib
@@ -84,6 +86,8 @@ def parse():
     ap.add_argument("--lnf-final", type=float, default=0.0,
                     help="override ln f_final of the configuration (--converge)")
     ap.add_argument("--save", default="", help="npz for ln g and jackknife errors (--converge)")
+    ap.add_argument("--balanced", action="store_true",
+                    help="--converge on the run-time balanced split planned from a pre-run")
     ap.add_argument("--copy-reference", action="store_true",
                     help="only copy a 512 MiB device buffer 3 times (HBM counter calibration)")
     return ap.parse_args()
@@ -164,6 +168,34 @@ def cv_peak(ctx, i, T):
     return float(T[k] + off * h), float(y1 - 0.25 * (y0 - y2) * off)
 
 
+def balanced_split(cfg, R, alpha, max_s):
+    """Run-time balanced windows (Fig. 1b) for `cfg`: a pre-run of R
+    instances with the equal split, other seeds, stopped after the first WL
+    iteration (ln f_final = ln f_0 / 2), gives each window's first-iteration
+    steps; rewl_balanced_windows turns their mean into window edges.
+    Returns ([(lo, hi)] * R, pre-run summary)."""
+    from paper_1402_2328_amd import rewl
+    from paper_1402_2328_amd import workloads as WL
+    F = cfg["flips_per_exchange"]
+    pre_cfg = dict(cfg, lnf_final=cfg["lnf_init"] / 2, seed=cfg["seed"] + 1000,
+                   schedule=WL.HALVING)
+    ctx = rewl.Context([WL.rewl_params_of(pre_cfg)] * R)
+    ctx.autotune(F)
+    done_at, cycles, wall = run_to_convergence(ctx, R, F, max_s, "balanced pre-run")
+    steps = []
+    for i in sorted(done_at):
+        _, sm = ctx.get_schedule(i)
+        steps.append((sm[:, 0] + 1) * F)
+    g = ctx.geometry[0]
+    mean = np.mean(np.array(steps, float), axis=0)
+    lo, hi = rewl.balanced_windows(g["nbins"], g["h"], g["lo"], g["hi"], mean,
+                                   overlap=tuple(cfg["overlap"]), alpha=alpha)
+    ctx.close()
+    pre = {"instances": len(steps), "cycles": cycles, "wall_s": wall,
+           "first_iteration_steps_mean": [float(x) for x in mean]}
+    return [(lo, hi)] * R, pre
+
+
 def converge(a):
     """Runs R instances of a configuration to ln f <= lnf_final and reports
     time to convergence, C_V peaks (Potts) and, for --config cfg34, the
@@ -186,13 +218,17 @@ def converge(a):
         cfg = dict(cfg, schedule=sched)
         if a.lnf_final > 0:
             cfg["lnf_final"] = a.lnf_final
-        ctx = rewl.Context([WL.rewl_params_of(cfg)] * R)
+        windows, pre = None, None
+        if a.balanced:
+            windows, pre = balanced_split(cfg, R, a.alpha, a.max_minutes * 60)
+        ctx = rewl.Context([WL.rewl_params_of(cfg)] * R, windows=windows)
         plan = ctx.autotune(cfg["flips_per_exchange"])
         done_at, cycles, wall = run_to_convergence(ctx, R, cfg["flips_per_exchange"],
                                                    a.max_minutes * 60 / len(runs), tag)
         g = ctx.geometry[0]
         N = g["N"]
         res = {"precision": tag, "lnf_final": cfg["lnf_final"], "launch": plan,
+               "windows_lo": [int(x) for x in g["lo"]], "balanced_prerun": pre,
                "converged": len(done_at), "cycles_run": cycles, "wall_s_all": wall,
                "wall_s_median": float(np.median(list(done_at.values()))) if done_at else None,
                "cycles_to_converge": sorted(int(ctx.status(i)["done_merge"]) for i in done_at)}

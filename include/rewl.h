@@ -127,20 +127,25 @@ int rewl_run_sweeps(rewl_ctx* ctx, int64_t flips);
  * 0 = Ising L <= 32, 1 = Ising 32 < L <= 64, 2 = Potts.  For class cls (-1:
  * all classes) keep page_bins ln g bins of each walker's window in LDS (the
  * rest stays in device memory; the page follows the walker) and put
- * walkers_per_group walkers in each 64-lane workgroup; 0 picks the default
- * (the largest page that lets four workgroups share a compute unit).
- * page_bins is rounded up to a power of two, at least 16 (32 for a class
- * with q >= 3 Potts instances) and at most the power of two that holds the
- * class's largest window.  Results do not depend on the shape, only speed
- * does.  out: NULL or 12 entries, per class {page_bins, walkers_per_group,
- * LDS bytes per workgroup, workgroups}.  Synchronises.  Errors: INVAL
- * (shape does not fit in LDS), HIP. */
+ * walkers_per_group walkers in each workgroup; 0 picks the default (the
+ * largest page that lets four workgroups share a compute unit).  page_bins
+ * is rounded up to a power of two, at least 16 (32 for a class with q >= 3
+ * Potts instances) and at most the power of two that holds the class's
+ * largest window.  rng_producer: 1 gives each workgroup a second
+ * wavefront that computes the walkers' random numbers ahead of them (for
+ * launches with few walkers, whose time is the walkers' serial chain), 0
+ * none, -1 the default (a producer when the class has no more workgroups
+ * than the GPU has compute units).  Results do not depend on the shape,
+ * only speed does.  out: NULL or 15 entries, per class {page_bins,
+ * walkers_per_group, LDS bytes per workgroup, workgroups, rng_producer}.
+ * Synchronises.  Errors: INVAL (shape does not fit in LDS), HIP. */
 int rewl_set_launch(rewl_ctx* ctx, int32_t cls, int32_t page_bins, int32_t walkers_per_group,
-                    int32_t* out);
+                    int32_t rng_producer, int32_t* out);
 
-/* Measures `repeats` sweeps of `flips` attempts for each candidate page
- * size (every allowed power of two) of every class, class by class with the
- * other classes at their best page so far, and keeps the fastest.  Sweeps
+/* Measures `repeats` sweeps of `flips` attempts for each candidate shape
+ * (every allowed power-of-two page, with and without the RNG producer) of
+ * every class, class by class with the other classes at their best shape so
+ * far, and keeps the fastest.  Sweeps
  * of different classes run concurrently, so every candidate is timed on
  * the whole batch.
  * The simulation state is saved to host memory first and restored

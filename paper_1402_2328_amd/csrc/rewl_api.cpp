@@ -218,6 +218,7 @@ int build_layout(const rewl_params* params, int32_t n, const int32_t* wlo, const
 // that still lets T = 4 (else 3, 2, 1) full workgroups share a compute unit.
 struct ClassPlan {
   int32_t G = 0, P = 0, count = 0, offset = 0;
+  int32_t prod = 0;  // RNG producer wavefront per workgroup
   size_t lds_bytes = 0;
 };
 struct LaunchPlan {
@@ -239,7 +240,22 @@ void page_range(const Layout& Lo, int cls, int& pmin, int& pmax) {
   pmin = std::min(Lo.potts3[cls] ? 32 : 16, pmax);
 }
 
-int plan_class(const Layout& Lo, int cls, int lds_budget, int page_req, int g_req, ClassPlan& cp) {
+// LDS bytes of a workgroup of G walkers with page P; with a producer the
+// RNG double buffer and a flag word follow the page.
+size_t lds_of(int lat, int G, int P, int prod) {
+  return (size_t)G * (lat + 12 * P) + (prod ? (size_t)2 * kRngChunk * G * 16 + 16 : 0);
+}
+
+int n_compute_units() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+    return v;
+  return 256;  // MI355X
+}
+
+int plan_class(const Layout& Lo, int cls, int lds_budget, int page_req, int g_req, int prod_req,
+               ClassPlan& cp) {
   cp = ClassPlan();
   if (Lo.walkers[cls] == 0) return REWL_OK;
   const int lat = 4 * Lo.lat_words[cls];
@@ -260,11 +276,16 @@ int plan_class(const Layout& Lo, int cls, int lds_budget, int page_req, int g_re
     if (P == 0) P = pmin;
   }
   if (g_req > 0) G = std::min(g_req, kSweepWave);
-  G = std::min(G, lds_budget / (lat + 12 * P));
-  if (G < 1) return REWL_E_INVAL;
+  // producer by default when the class's workgroups do not outnumber the
+  // compute units (the walkers' chain, not issue, then bounds the sweep)
+  int prod = prod_req;
+  if (prod < 0) prod = (Lo.walkers[cls] + G - 1) / G <= n_compute_units() ? 1 : 0;
+  while (G > 1 && lds_of(lat, G, P, prod) > (size_t)lds_budget) --G;
+  if (lds_of(lat, G, P, prod) > (size_t)lds_budget) return REWL_E_INVAL;
   cp.G = G;
   cp.P = P;
-  cp.lds_bytes = (size_t)G * (lat + 12 * P);
+  cp.prod = prod;
+  cp.lds_bytes = lds_of(lat, G, P, prod);
   return REWL_OK;
 }
 
@@ -294,7 +315,7 @@ void fill_table(const Layout& Lo, LaunchPlan& pl) {
 int plan_launch(const Layout& Lo, int lds_budget, int page_req, int g_req, LaunchPlan& pl) {
   pl = LaunchPlan();
   for (int cls = 0; cls < 3; ++cls) {
-    int rc = plan_class(Lo, cls, lds_budget, page_req, g_req, pl.cls[cls]);
+    int rc = plan_class(Lo, cls, lds_budget, page_req, g_req, -1, pl.cls[cls]);
     if (rc) return rc;
   }
   fill_table(Lo, pl);
@@ -392,7 +413,7 @@ hipError_t enqueue_sweeps(rewl_ctx* c, int64_t flips, int only_class = -1) {
     const ClassPlan& cp = c->plan.cls[cls];
     SweepShape sh{cp.G, c->lo.lat_words[cls], cp.P, cp.offset};
     hipStream_t s = (fork && i > 0) ? c->side[i - 1] : c->stream;
-    e = launch_sweep_class(c->P, cls, sh, cp.count, flips, cp.lds_bytes, s);
+    e = launch_sweep_class(c->P, cls, sh, cp.count, flips, cp.lds_bytes, cp.prod != 0, s);
   }
   if (fork) {
     for (int i = 1; i < n && e == hipSuccess; ++i) {
@@ -557,10 +578,11 @@ int install_plan(rewl_ctx* c, const LaunchPlan& pl) {
 void plan_out(const LaunchPlan& pl, int32_t* out) {
   if (!out) return;
   for (int cls = 0; cls < 3; ++cls) {
-    out[4 * cls + 0] = pl.cls[cls].P;
-    out[4 * cls + 1] = pl.cls[cls].G;
-    out[4 * cls + 2] = (int32_t)pl.cls[cls].lds_bytes;
-    out[4 * cls + 3] = pl.cls[cls].count;
+    out[5 * cls + 0] = pl.cls[cls].P;
+    out[5 * cls + 1] = pl.cls[cls].G;
+    out[5 * cls + 2] = (int32_t)pl.cls[cls].lds_bytes;
+    out[5 * cls + 3] = pl.cls[cls].count;
+    out[5 * cls + 4] = pl.cls[cls].prod;
   }
 }
 
@@ -569,12 +591,14 @@ void plan_out(const LaunchPlan& pl, int32_t* out) {
 extern "C" {
 
 int rewl_set_launch(rewl_ctx* c, int32_t cls, int32_t page_bins, int32_t walkers_per_group,
-                    int32_t* out) {
+                    int32_t rng_producer, int32_t* out) {
   if (!c || page_bins < 0 || walkers_per_group < 0 || cls < -1 || cls > 2) return REWL_E_INVAL;
+  if (rng_producer < -1 || rng_producer > 1) return REWL_E_INVAL;
   LaunchPlan pl = c->plan;
   for (int k = 0; k < 3; ++k) {
     if (cls >= 0 && k != cls) continue;
-    int rc = plan_class(c->lo, k, lds_budget_bytes(), page_bins, walkers_per_group, pl.cls[k]);
+    int rc = plan_class(c->lo, k, lds_budget_bytes(), page_bins, walkers_per_group, rng_producer,
+                        pl.cls[k]);
     if (rc) return rc;
   }
   fill_table(c->lo, pl);
@@ -602,9 +626,12 @@ int rewl_autotune(rewl_ctx* c, int64_t flips, int32_t repeats, int32_t* out) {
     page_range(L, cls, pmin, pmax);
     for (int p = pmin; p <= pmax; p <<= 1) cands.push_back(p);
     float best_ms = -1.0f;
-    for (int p : cands) {
+    std::vector<std::pair<int, int>> shapes;  // (page, producer)
+    for (int p : cands)
+      for (int prod = 0; prod < 2; ++prod) shapes.push_back({p, prod});
+    for (const auto& shp : shapes) {
       LaunchPlan pl = best;
-      if (plan_class(L, cls, budget, p, 0, pl.cls[cls])) continue;
+      if (plan_class(L, cls, budget, shp.first, 0, shp.second, pl.cls[cls])) continue;
       fill_table(L, pl);
       rc = install_plan(c, pl);
       if (!rc) rc = hip_rc(hipMemcpyAsync(c->ws, snap.data(), c->lo.o_wg, hipMemcpyHostToDevice, c->stream));

@@ -14,7 +14,8 @@ namespace rewl {
 constexpr int kMaxStages = 64;    // stage bookkeeping per window
 constexpr int kMaxWalkersPerWindow = 64;
 constexpr int kMaxL = 64;
-constexpr int kSweepWave = 64;    // one wavefront per sweep workgroup
+constexpr int kSweepWave = 64;    // walkers' wavefront of a sweep workgroup
+constexpr int kRngChunk = 16;     // attempts per hand-over of the RNG producer
 constexpr int kMaxTemps = 16384;  // rewl_thermo temperatures per call
 
 enum Model : int32_t { kIsing = 0, kPotts = 1 };
@@ -102,9 +103,10 @@ struct SweepShape {
 // Launchers (kernels TU).  All enqueue on `s` and return the launch status.
 hipError_t launch_init(const DevPtrs& P, hipStream_t s);
 // One sweep kernel class: 0 = Ising L <= 32, 1 = Ising 32 < L <= 64,
-// 2 = Potts; n_wg workgroups starting at sh.wg_offset of the table.
+// 2 = Potts; n_wg workgroups starting at sh.wg_offset of the table;
+// producer: a second wavefront per workgroup computes the random numbers.
 hipError_t launch_sweep_class(const DevPtrs& P, int cls, SweepShape sh, int32_t n_wg, int64_t flips,
-                              size_t lds_bytes, hipStream_t s);
+                              size_t lds_bytes, bool producer, hipStream_t s);
 hipError_t launch_merge(const DevPtrs& P, hipStream_t s);
 hipError_t launch_exchange(const DevPtrs& P, hipStream_t s);
 hipError_t launch_join(const DevPtrs& P, int32_t instance, int32_t normalise, hipStream_t s);

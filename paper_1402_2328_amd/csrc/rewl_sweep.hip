@@ -40,19 +40,37 @@ __device__ __forceinline__ T* at_off(T* base, uint32_t byte_off) {
   return reinterpret_cast<T*>(reinterpret_cast<unsigned char*>(base) + byte_off);
 }
 
-template <int MODEL, int PREC, int ROWW>
-__global__ __launch_bounds__(kSweepWave) void k_sweep(DevPtrs P, SweepShape sh, int64_t flips) {
+// PROD: the workgroup has a second wavefront that computes the Philox
+// blocks of the walkers' coming attempts, kRngChunk at a time, into a
+// double buffer in LDS (chunk c in half c mod 2) while the walker wavefront
+// consumes the previous chunk; one workgroup barrier per chunk hands over.
+// This takes the RNG off the walkers' serial chain when few walkers share
+// the chip; the blocks are the ones the walkers would compute themselves.
+template <int MODEL, int PREC, int ROWW, bool PROD>
+__global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(DevPtrs P, SweepShape sh,
+                                                                                int64_t flips) {
   extern __shared__ __align__(16) unsigned char lds[];
   const WgDesc wg = P.wg[sh.wg_offset + blockIdx.x];
   const InstDesc& Ig = P.inst[wg.inst];
-  if (P.ist[wg.inst].done || P.ist[wg.inst].error) return;
-  const int lane = threadIdx.x;
-  if (lane >= wg.count) return;
-
   const int S = sh.stride;
   const int NWL = sh.nw;   // lattice words per lane
   const int PG = sh.page;  // page slots per lane, a power of two
   const int PM = PG - 1;
+  const int tid = threadIdx.x;
+  const int lane = tid & (kSweepWave - 1);
+  // RNG double buffer [2][kRngChunk][S] after the page, then a flag word
+  uint4* rbuf = reinterpret_cast<uint4*>(lds + (size_t)4 * NWL * S + (size_t)12 * PG * S);
+  bool skip = P.ist[wg.inst].done || P.ist[wg.inst].error;
+  if (PROD) {
+    // one decision for both wavefronts: both must reach every barrier
+    int* flag = reinterpret_cast<int*>(rbuf + (size_t)2 * kRngChunk * S);
+    if (tid == 0) *flag = skip ? 1 : 0;
+    __syncthreads();
+    skip = *flag != 0;
+  }
+  if (skip) return;
+  const bool active = lane < wg.count;
+  const int64_t nchunks = (flips + kRngChunk - 1) / kRngChunk;
   uint32_t* lat = reinterpret_cast<uint32_t*>(lds);                           // [NWL][S]
   unsigned char* latb = lds;                                                   // byte view (Potts)
   unsigned char* pg = lds + (size_t)4 * NWL * S;
@@ -72,6 +90,28 @@ __global__ __launch_bounds__(kSweepWave) void k_sweep(DevPtrs P, SweepShape sh, 
   const int Lm = L - 1;
   const int lgL = 31 - __builtin_clz((unsigned)L);
 
+  if (PROD && tid >= kSweepWave) {
+    // ---- RNG producer ----
+    const int gp = wg.slot_first + lane;
+    const int locp = gp - Ig.slot_base;
+    const uint64_t att0 = active ? P.att[gp] : 0;
+    auto fill = [&](int64_t c) {
+      uint4* dst = rbuf + (size_t)(c & 1) * kRngChunk * S + lane;
+      const int n = (flips - c * kRngChunk) < kRngChunk ? (int)(flips - c * kRngChunk) : kRngChunk;
+      for (int i = 0; i < n; ++i) {
+        const uint64_t a = att0 + (uint64_t)(c * kRngChunk + i);
+        dst[(size_t)i * S] = philox10(make_uint4((uint32_t)a, (uint32_t)(a >> 32), (uint32_t)locp, tagw), k0, k1);
+      }
+    };
+    if (active && nchunks > 0) fill(0);
+    __syncthreads();
+    for (int64_t c = 0; c < nchunks; ++c) {
+      if (active && c + 1 < nchunks) fill(c + 1);
+      __syncthreads();
+    }
+    return;
+  }
+  if (!active) return;
   const int g = wg.slot_first + lane;
   const int loc = g - Ig.slot_base;
   const int w = loc / Ig.m;
@@ -99,9 +139,12 @@ __global__ __launch_bounds__(kSweepWave) void k_sweep(DevPtrs P, SweepShape sh, 
   int32_t E = P.E[g];
   uint64_t att = P.att[g];
   int bin = (E - Ig.emin) >> bshift;
-  if (bin < lo || bin > hi) {  // only reachable through corrupted state
+  if (bin < lo || bin > hi) {
+    // only reachable through corrupted state: flag the instance and keep
+    // every access inside the window (the instance's results are void)
     atomicMin(&P.ist[wg.inst].error, -6);
-    return;
+    bin = bin < lo ? lo : hi;
+    E = Ig.emin + (bin << bshift);
   }
 
   // ---- stage in the lattice ----
@@ -176,8 +219,9 @@ __global__ __launch_bounds__(kSweepWave) void k_sweep(DevPtrs P, SweepShape sh, 
   // shadows of attempt t -- after the lattice reads are issued, after the
   // ln g read is issued, and beside the exponential.  sched_barrier keeps
   // the compiler from hoisting the slices back together.
-  uint4 r = philox10(make_uint4((uint32_t)att, (uint32_t)(att >> 32), (uint32_t)loc, tagw), k0, k1);
-  for (int64_t t = 0; t < flips; ++t) {
+  // One attempt with Philox block r; without a producer it also computes
+  // rn, the block of the next attempt, in slices.
+  auto attempt = [&](const uint4 r, uint4& rn) {
     const uint64_t an = att + 1;
     const uint4 cn = make_uint4((uint32_t)an, (uint32_t)(an >> 32), (uint32_t)loc, tagw);
     const int site = (int)__umulhi(r.x, (uint32_t)N);
@@ -200,7 +244,6 @@ __global__ __launch_bounds__(kSweepWave) void k_sweep(DevPtrs P, SweepShape sh, 
     int dE, db, nv = 0;
     int widx = 0;
     uint32_t wrow = 0;
-    uint4 rn;
     if (MODEL == kIsing) {
       // bit b of a row word: spin at x = 32 * part + b is +1
       int s0, a, b, c, d;
@@ -210,8 +253,10 @@ __global__ __launch_bounds__(kSweepWave) void k_sweep(DevPtrs P, SweepShape sh, 
         const uint32_t wu = lat[prow(yu)];
         const uint32_t wd = lat[prow(yd)];
         __builtin_amdgcn_sched_barrier(0);
-        rn = philox_rounds<0, 4>(cn, k0, k1);
-        REWL_PIN4(rn);
+        if constexpr (!PROD) {
+          rn = philox_rounds<0, 4>(cn, k0, k1);
+          REWL_PIN4(rn);
+        }
         __builtin_amdgcn_sched_barrier(0);
         s0 = (wrow >> x) & 1;
         a = (wrow >> xr) & 1;
@@ -225,8 +270,10 @@ __global__ __launch_bounds__(kSweepWave) void k_sweep(DevPtrs P, SweepShape sh, 
         const uint32_t wu = lat[prow(2 * yu + px)];
         const uint32_t wd = lat[prow(2 * yd + px)];
         __builtin_amdgcn_sched_barrier(0);
-        rn = philox_rounds<0, 4>(cn, k0, k1);
-        REWL_PIN4(rn);
+        if constexpr (!PROD) {
+          rn = philox_rounds<0, 4>(cn, k0, k1);
+          REWL_PIN4(rn);
+        }
         __builtin_amdgcn_sched_barrier(0);
         wrow = px ? r1 : r0;
         s0 = (wrow >> (x & 31)) & 1;
@@ -247,8 +294,10 @@ __global__ __launch_bounds__(kSweepWave) void k_sweep(DevPtrs P, SweepShape sh, 
       const int c = (int)latb[pbyte(__mul24(yd, L) + x)];
       const int d = (int)latb[pbyte(__mul24(yu, L) + x)];
       __builtin_amdgcn_sched_barrier(0);
-      rn = philox_rounds<0, 4>(cn, k0, k1);
-      REWL_PIN4(rn);
+      if constexpr (!PROD) {
+        rn = philox_rounds<0, 4>(cn, k0, k1);
+        REWL_PIN4(rn);
+      }
       __builtin_amdgcn_sched_barrier(0);
       int v = s0 + 1 + (int)__umulhi(r.y, (uint32_t)(q - 1));
       v = (v >= q) ? v - q : v;
@@ -264,24 +313,32 @@ __global__ __launch_bounds__(kSweepWave) void k_sweep(DevPtrs P, SweepShape sh, 
     if (PREC == kFP64) {
       const double ln = plg[jn];
       __builtin_amdgcn_sched_barrier(0);
-      rn = philox_rounds<4, 7>(rn, k0, k1);
-      REWL_PIN4(rn);
+      if constexpr (!PROD) {
+        rn = philox_rounds<4, 7>(rn, k0, k1);
+        REWL_PIN4(rn);
+      }
       __builtin_amdgcn_sched_barrier(0);
       const bool a = accept64_flat(r.z, r.w, lcur - ln);
-      rn = philox_rounds<7, 10>(rn, k0, k1);
-      REWL_PIN4(rn);
+      if constexpr (!PROD) {
+        rn = philox_rounds<7, 10>(rn, k0, k1);
+        REWL_PIN4(rn);
+      }
       acc = inwin && a;
       lcur = acc ? ln : lcur;
     } else {
       const float nh = plh[jn];
       const float nl = pll[jn];
       __builtin_amdgcn_sched_barrier(0);
-      rn = philox_rounds<4, 7>(rn, k0, k1);
-      REWL_PIN4(rn);
+      if constexpr (!PROD) {
+        rn = philox_rounds<4, 7>(rn, k0, k1);
+        REWL_PIN4(rn);
+      }
       __builtin_amdgcn_sched_barrier(0);
       const bool a = accept32_flat(r.z >> 8, (hcur - nh) + (lcur_lo - nl));
-      rn = philox_rounds<7, 10>(rn, k0, k1);
-      REWL_PIN4(rn);
+      if constexpr (!PROD) {
+        rn = philox_rounds<7, 10>(rn, k0, k1);
+        REWL_PIN4(rn);
+      }
       acc = inwin && a;
       hcur = acc ? nh : hcur;
       lcur_lo = acc ? nl : lcur_lo;
@@ -359,8 +416,31 @@ __global__ __launch_bounds__(kSweepWave) void k_sweep(DevPtrs P, SweepShape sh, 
         pend_n = shn;
       }
     }
-    r = rn;
+    (void)cn;
     ++att;
+  };
+
+  if constexpr (!PROD) {
+    uint4 r = philox10(make_uint4((uint32_t)att, (uint32_t)(att >> 32), (uint32_t)loc, tagw), k0, k1);
+    for (int64_t t = 0; t < flips; ++t) {
+      uint4 rn;
+      attempt(r, rn);
+      r = rn;
+    }
+  } else {
+    __syncthreads();  // chunk 0 is in the buffer
+    for (int64_t c = 0; c < nchunks; ++c) {
+      const uint4* src = rbuf + (size_t)(c & 1) * kRngChunk * S + lane;
+      const int n = (flips - c * kRngChunk) < kRngChunk ? (int)(flips - c * kRngChunk) : kRngChunk;
+      uint4 r = src[0];
+      for (int i = 0; i < n; ++i) {
+        const uint4 rnext = src[(size_t)(i + 1 < n ? i + 1 : i) * S];
+        uint4 unused;
+        attempt(r, unused);
+        r = rnext;
+      }
+      __syncthreads();  // chunk c consumed, chunk c + 1 written
+    }
   }
 
   // ---- stage out ----
@@ -411,9 +491,13 @@ __global__ __launch_bounds__(kSweepWave) void k_sweep(DevPtrs P, SweepShape sh, 
 }
 
 hipError_t prepare_sweep_lds(size_t lds_bytes) {
-  const void* fns[] = {(const void*)k_sweep<kIsing, kFP64, 1>, (const void*)k_sweep<kIsing, kFP64, 2>,
-                       (const void*)k_sweep<kPotts, kFP64, 0>, (const void*)k_sweep<kIsing, kFP32C, 1>,
-                       (const void*)k_sweep<kIsing, kFP32C, 2>, (const void*)k_sweep<kPotts, kFP32C, 0>};
+  const void* fns[] = {
+      (const void*)k_sweep<kIsing, kFP64, 1, false>,  (const void*)k_sweep<kIsing, kFP64, 2, false>,
+      (const void*)k_sweep<kPotts, kFP64, 0, false>,  (const void*)k_sweep<kIsing, kFP32C, 1, false>,
+      (const void*)k_sweep<kIsing, kFP32C, 2, false>, (const void*)k_sweep<kPotts, kFP32C, 0, false>,
+      (const void*)k_sweep<kIsing, kFP64, 1, true>,   (const void*)k_sweep<kIsing, kFP64, 2, true>,
+      (const void*)k_sweep<kPotts, kFP64, 0, true>,   (const void*)k_sweep<kIsing, kFP32C, 1, true>,
+      (const void*)k_sweep<kIsing, kFP32C, 2, true>,  (const void*)k_sweep<kPotts, kFP32C, 0, true>};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
@@ -421,19 +505,26 @@ hipError_t prepare_sweep_lds(size_t lds_bytes) {
   return hipSuccess;
 }
 
-hipError_t launch_sweep_class(const DevPtrs& P, int cls, SweepShape sh, int32_t n_wg, int64_t flips,
-                              size_t lds_bytes, hipStream_t s) {
-  if (n_wg <= 0) return hipSuccess;
-  const dim3 grid(n_wg), blk(kSweepWave);
+template <bool PROD>
+void launch_class(const DevPtrs& P, int cls, SweepShape sh, dim3 grid, int64_t flips, size_t lds_bytes,
+                  hipStream_t s) {
+  const dim3 blk(PROD ? 2 * kSweepWave : kSweepWave);
   if (P.prec == kFP64) {
-    if (cls == 0) hipLaunchKernelGGL((k_sweep<kIsing, kFP64, 1>), grid, blk, lds_bytes, s, P, sh, flips);
-    if (cls == 1) hipLaunchKernelGGL((k_sweep<kIsing, kFP64, 2>), grid, blk, lds_bytes, s, P, sh, flips);
-    if (cls == 2) hipLaunchKernelGGL((k_sweep<kPotts, kFP64, 0>), grid, blk, lds_bytes, s, P, sh, flips);
+    if (cls == 0) hipLaunchKernelGGL((k_sweep<kIsing, kFP64, 1, PROD>), grid, blk, lds_bytes, s, P, sh, flips);
+    if (cls == 1) hipLaunchKernelGGL((k_sweep<kIsing, kFP64, 2, PROD>), grid, blk, lds_bytes, s, P, sh, flips);
+    if (cls == 2) hipLaunchKernelGGL((k_sweep<kPotts, kFP64, 0, PROD>), grid, blk, lds_bytes, s, P, sh, flips);
   } else {
-    if (cls == 0) hipLaunchKernelGGL((k_sweep<kIsing, kFP32C, 1>), grid, blk, lds_bytes, s, P, sh, flips);
-    if (cls == 1) hipLaunchKernelGGL((k_sweep<kIsing, kFP32C, 2>), grid, blk, lds_bytes, s, P, sh, flips);
-    if (cls == 2) hipLaunchKernelGGL((k_sweep<kPotts, kFP32C, 0>), grid, blk, lds_bytes, s, P, sh, flips);
+    if (cls == 0) hipLaunchKernelGGL((k_sweep<kIsing, kFP32C, 1, PROD>), grid, blk, lds_bytes, s, P, sh, flips);
+    if (cls == 1) hipLaunchKernelGGL((k_sweep<kIsing, kFP32C, 2, PROD>), grid, blk, lds_bytes, s, P, sh, flips);
+    if (cls == 2) hipLaunchKernelGGL((k_sweep<kPotts, kFP32C, 0, PROD>), grid, blk, lds_bytes, s, P, sh, flips);
   }
+}
+
+hipError_t launch_sweep_class(const DevPtrs& P, int cls, SweepShape sh, int32_t n_wg, int64_t flips,
+                              size_t lds_bytes, bool producer, hipStream_t s) {
+  if (n_wg <= 0) return hipSuccess;
+  if (producer) launch_class<true>(P, cls, sh, dim3(n_wg), flips, lds_bytes, s);
+  else launch_class<false>(P, cls, sh, dim3(n_wg), flips, lds_bytes, s);
   return hipGetLastError();
 }
 

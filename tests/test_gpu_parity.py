@@ -170,6 +170,22 @@ def test_thermo_matches_oracle():
     assert np.allclose(Cg, Co, rtol=1e-10, atol=1e-9)
 
 
+@pytest.mark.parametrize("prod", [0, 1])
+def test_flips_not_a_multiple_of_the_rng_chunk(prod):
+    """Sweeps of 1, 15, 17 and 1001 attempts (the producer hands over 16 at
+    a time) with and without the producer wavefront."""
+    cfg = SMALL["ising_L8_h4_m2"]
+    ctx = gpu_context([cfg])
+    ctx.set_launch(rng_producer=prod)
+    sim = oracle_sim(cfg)
+    for F in (1, 15, 17, 1001):
+        ctx.run_sweeps(F)
+        ctx.merge()
+        ctx.exchange()
+        oracle_cycle(sim, F)
+        compare_state(ctx, 0, sim)
+
+
 def test_zero_flips_is_a_no_op_and_negative_is_rejected():
     cfg = SMALL["ising_L8_h4_m2"]
     ctx = gpu_context([cfg])
@@ -195,22 +211,23 @@ def test_unreachable_window_is_reported_on_both_sides():
     assert ctx.running() == 0
 
 
-@pytest.mark.parametrize("name,page,group", [("ising_L16_h5_m4", 16, 0), ("ising_L16_h5_m4", 0, 5),
-                                             ("ising_L16_h5_m4", 64, 0),
-                                             ("potts_q5_L12_h9_m7_ragged", 32, 13),
-                                             ("potts_q10_L8_h4_m4", 32, 3),
-                                             ("ising_L40_h6_m2_tworow", 16, 0),
-                                             ("ising_L8_fp32c", 16, 0),
-                                             ("potts_q10_L8_fp32c", 32, 7)])
-def test_page_size_and_group_shape_do_not_change_results(name, page, group):
+@pytest.mark.parametrize("name,page,group,prod", [("ising_L16_h5_m4", 16, 0, 0), ("ising_L16_h5_m4", 0, 5, 1),
+                                                  ("ising_L16_h5_m4", 64, 0, 1),
+                                                  ("potts_q5_L12_h9_m7_ragged", 32, 13, 1),
+                                                  ("potts_q10_L8_h4_m4", 32, 3, 0),
+                                                  ("ising_L40_h6_m2_tworow", 16, 0, 1),
+                                                  ("ising_L8_fp32c", 16, 0, 1),
+                                                  ("potts_q10_L8_fp32c", 32, 7, 0)])
+def test_page_size_and_group_shape_do_not_change_results(name, page, group, prod):
     """Pages much smaller than the windows make the page follow the walker
-    through device memory at almost every move; results must not change."""
+    through device memory at almost every move; with prod = 1 a second
+    wavefront supplies the random numbers.  Results must not change."""
     cfg = SMALL[name]
     ctx = gpu_context([cfg])
-    plan = ctx.set_launch(page_bins=page, walkers_per_group=group)
+    plan = ctx.set_launch(page_bins=page, walkers_per_group=group, rng_producer=prod)
     print(f"[parity] {name}: plan {plan}", flush=True)
     (p,) = plan.values()
-    assert p["page_bins"] & (p["page_bins"] - 1) == 0
+    assert p["page_bins"] & (p["page_bins"] - 1) == 0 and p["rng_producer"] == prod
     if page:
         assert p["page_bins"] == page
     sim = oracle_sim(cfg)
