@@ -81,7 +81,8 @@ def parse():
     ap.add_argument("--speedup", action="store_true")
     ap.add_argument("--L", type=int, default=32, help="lattice size (--speedup)")
     ap.add_argument("--hs", default="1,2,4,8,16,32", help="window counts (--speedup)")
-    ap.add_argument("--walkers", type=int, default=1, help="walkers per window (--speedup)")
+    ap.add_argument("--walkers", type=int, default=None,
+                    help="walkers per window (--speedup: default 1; --converge: the config's)")
     ap.add_argument("--alpha", type=float, default=2.0, help="cost exponent of the balanced split")
     ap.add_argument("--lnf-final", type=float, default=0.0,
                     help="override ln f_final of the configuration (--converge)")
@@ -211,13 +212,15 @@ def converge(a):
             "cfg34": [("fp64", WL.CFG3), ("fp32c", WL.CFG4)]}[name]
     sched = WL.ONE_OVER_T if a.schedule == "1t" else WL.HALVING
     out = {"metric": "time to ln f <= ln f_final", "config": name, "schedule": a.schedule,
-           "instances": R, "runs": {}}
+           "instances": R, "walkers_per_window": a.walkers, "balanced": a.balanced, "runs": {}}
     saved = {}
     lng_by_run = {}
     for tag, cfg in runs:
         cfg = dict(cfg, schedule=sched)
         if a.lnf_final > 0:
             cfg["lnf_final"] = a.lnf_final
+        if a.walkers:
+            cfg["walkers_per_window"] = a.walkers
         windows, pre = None, None
         if a.balanced:
             windows, pre = balanced_split(cfg, R, a.alpha, a.max_minutes * 60)
@@ -283,7 +286,7 @@ def speedup(a):
     from paper_1402_2328_amd import rewl
     from paper_1402_2328_amd import workloads as WL
     hs = [int(x) for x in a.hs.split(",")]
-    R, F, m = a.replicas, a.flips, a.walkers
+    R, F, m = a.replicas, a.flips, (a.walkers or 1)
     base = WL.config(WL.ISING, a.L, n_windows=1, walkers_per_window=m, lnf_final=0.5, flips=F)
 
     def measure(tag, split, seed0):

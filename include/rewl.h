@@ -135,15 +135,21 @@ int rewl_run_sweeps(rewl_ctx* ctx, int64_t flips);
  * wavefront that computes the walkers' random numbers ahead of them (for
  * launches with few walkers, whose time is the walkers' serial chain), 0
  * none, -1 the default (a producer when the class has no more workgroups
- * than the GPU has compute units).  Results do not depend on the shape,
- * only speed does.  out: NULL or 15 entries, per class {page_bins,
- * walkers_per_group, LDS bytes per workgroup, workgroups, rng_producer}.
- * Synchronises.  Errors: INVAL (shape does not fit in LDS), HIP. */
+ * than the GPU has compute units).  potts_nibbles (Potts class, every
+ * q <= 16): 1 keeps spins in LDS as 4-bit nibbles (half the lattice, more
+ * workgroups per compute unit), 0 as bytes (shorter chain per attempt), -1
+ * the default (nibbles when the class has more workgroups than compute
+ * units); ignored where it does not apply.  Results do not depend on the
+ * shape, only speed does.  out: NULL
+ * or 18 entries, per class {page_bins, walkers_per_group, LDS bytes per
+ * workgroup, workgroups, rng_producer, potts_nibbles}.  Synchronises.
+ * Errors: INVAL (shape does not fit in LDS), HIP. */
 int rewl_set_launch(rewl_ctx* ctx, int32_t cls, int32_t page_bins, int32_t walkers_per_group,
-                    int32_t rng_producer, int32_t* out);
+                    int32_t rng_producer, int32_t potts_nibbles, int32_t* out);
 
 /* Measures `repeats` sweeps of `flips` attempts for each candidate shape
- * (every allowed power-of-two page, with and without the RNG producer) of
+ * (every allowed power-of-two page, with and without the RNG producer, Potts
+ * spins as nibbles or bytes) of
  * every class, class by class with the other classes at their best shape so
  * far, and keeps the fastest.  Sweeps
  * of different classes run concurrently, so every candidate is timed on

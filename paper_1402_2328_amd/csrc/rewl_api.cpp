@@ -37,7 +37,9 @@ struct Layout {
   // per sweep class (Ising L <= 32, Ising L <= 64, Potts): largest lattice
   // in the sweep's LDS format (32-bit words), largest window (bins), whether
   // a q >= 3 Potts instance is present, walkers
-  int32_t lat_words[3] = {0, 0, 0};
+  int32_t lat_words[3] = {0, 0, 0};      // with Potts spins as bytes
+  int32_t lat_words_nib[3] = {0, 0, 0};  // with Potts spins as nibbles
+  int32_t nib_ok[3] = {1, 1, 1};         // every Potts instance has q <= 16
   int32_t nb_max[3] = {0, 0, 0};
   int32_t potts3[3] = {0, 0, 0};
   int32_t walkers[3] = {0, 0, 0};
@@ -148,12 +150,16 @@ int build_layout(const rewl_params* params, int32_t n, const int32_t* wlo, const
       I.nbmax = std::max(I.nbmax, D.nb);
       Lo.win.push_back(D);
     }
-    // sweep LDS lattice: Ising bit rows (1 word per row for L <= 32, else 2),
-    // Potts bytes
     const int cls = I.model == REWL_POTTS ? 2 : (I.L <= 32 ? 0 : 1);
+    // sweep LDS lattice words: Ising bit rows (1 word per row for L <= 32,
+    // else 2), Potts bytes or nibbles
     int lw = I.model == REWL_ISING ? I.L * (I.L <= 32 ? 1 : 2) : (I.N + 3) / 4;
+    int lwn = I.model == REWL_ISING ? lw : (I.N + 7) / 8;
     lw += lw & 1;
+    lwn += lwn & 1;
     Lo.lat_words[cls] = std::max(Lo.lat_words[cls], lw);
+    Lo.lat_words_nib[cls] = std::max(Lo.lat_words_nib[cls], lwn);
+    if (I.model == REWL_POTTS && I.q > 16) Lo.nib_ok[cls] = 0;
     Lo.nb_max[cls] = std::max(Lo.nb_max[cls], I.nbmax);
     Lo.potts3[cls] |= (I.model == REWL_POTTS && I.q >= 3);
     Lo.walkers[cls] += I.W;
@@ -219,6 +225,7 @@ int build_layout(const rewl_params* params, int32_t n, const int32_t* wlo, const
 struct ClassPlan {
   int32_t G = 0, P = 0, count = 0, offset = 0;
   int32_t prod = 0;  // RNG producer wavefront per workgroup
+  int32_t nib = 0;   // Potts spins as nibbles
   size_t lds_bytes = 0;
 };
 struct LaunchPlan {
@@ -255,10 +262,16 @@ int n_compute_units() {
 }
 
 int plan_class(const Layout& Lo, int cls, int lds_budget, int page_req, int g_req, int prod_req,
-               ClassPlan& cp) {
+               int nib_req, ClassPlan& cp) {
   cp = ClassPlan();
   if (Lo.walkers[cls] == 0) return REWL_OK;
-  const int lat = 4 * Lo.lat_words[cls];
+  // Potts nibbles halve the lattice and so raise the workgroups per compute
+  // unit, at a little extra latency per attempt: by default when the class
+  // has more workgroups than the GPU has compute units
+  const bool many = (Lo.walkers[cls] + kSweepWave - 1) / kSweepWave > n_compute_units();
+  int nib = cls == 2 && Lo.nib_ok[cls] ? (nib_req < 0 ? (many ? 1 : 0) : nib_req) : 0;
+  if (nib_req == 1 && !(cls == 2 && Lo.nib_ok[cls])) nib = 0;
+  const int lat = 4 * (nib ? Lo.lat_words_nib[cls] : Lo.lat_words[cls]);
   int pmin, pmax;
   page_range(Lo, cls, pmin, pmax);
   int P = 0, G = kSweepWave;
@@ -285,6 +298,7 @@ int plan_class(const Layout& Lo, int cls, int lds_budget, int page_req, int g_re
   cp.G = G;
   cp.P = P;
   cp.prod = prod;
+  cp.nib = nib;
   cp.lds_bytes = lds_of(lat, G, P, prod);
   return REWL_OK;
 }
@@ -315,7 +329,7 @@ void fill_table(const Layout& Lo, LaunchPlan& pl) {
 int plan_launch(const Layout& Lo, int lds_budget, int page_req, int g_req, LaunchPlan& pl) {
   pl = LaunchPlan();
   for (int cls = 0; cls < 3; ++cls) {
-    int rc = plan_class(Lo, cls, lds_budget, page_req, g_req, -1, pl.cls[cls]);
+    int rc = plan_class(Lo, cls, lds_budget, page_req, g_req, -1, -1, pl.cls[cls]);
     if (rc) return rc;
   }
   fill_table(Lo, pl);
@@ -411,7 +425,7 @@ hipError_t enqueue_sweeps(rewl_ctx* c, int64_t flips, int only_class = -1) {
   for (int i = 0; i < n && e == hipSuccess; ++i) {
     const int cls = active[i];
     const ClassPlan& cp = c->plan.cls[cls];
-    SweepShape sh{cp.G, c->lo.lat_words[cls], cp.P, cp.offset};
+    SweepShape sh{cp.G, cp.nib ? c->lo.lat_words_nib[cls] : c->lo.lat_words[cls], cp.P, cp.offset, cp.nib};
     hipStream_t s = (fork && i > 0) ? c->side[i - 1] : c->stream;
     e = launch_sweep_class(c->P, cls, sh, cp.count, flips, cp.lds_bytes, cp.prod != 0, s);
   }
@@ -578,11 +592,12 @@ int install_plan(rewl_ctx* c, const LaunchPlan& pl) {
 void plan_out(const LaunchPlan& pl, int32_t* out) {
   if (!out) return;
   for (int cls = 0; cls < 3; ++cls) {
-    out[5 * cls + 0] = pl.cls[cls].P;
-    out[5 * cls + 1] = pl.cls[cls].G;
-    out[5 * cls + 2] = (int32_t)pl.cls[cls].lds_bytes;
-    out[5 * cls + 3] = pl.cls[cls].count;
-    out[5 * cls + 4] = pl.cls[cls].prod;
+    out[6 * cls + 0] = pl.cls[cls].P;
+    out[6 * cls + 1] = pl.cls[cls].G;
+    out[6 * cls + 2] = (int32_t)pl.cls[cls].lds_bytes;
+    out[6 * cls + 3] = pl.cls[cls].count;
+    out[6 * cls + 4] = pl.cls[cls].prod;
+    out[6 * cls + 5] = pl.cls[cls].nib;
   }
 }
 
@@ -591,14 +606,15 @@ void plan_out(const LaunchPlan& pl, int32_t* out) {
 extern "C" {
 
 int rewl_set_launch(rewl_ctx* c, int32_t cls, int32_t page_bins, int32_t walkers_per_group,
-                    int32_t rng_producer, int32_t* out) {
+                    int32_t rng_producer, int32_t potts_nibbles, int32_t* out) {
   if (!c || page_bins < 0 || walkers_per_group < 0 || cls < -1 || cls > 2) return REWL_E_INVAL;
-  if (rng_producer < -1 || rng_producer > 1) return REWL_E_INVAL;
+  if (rng_producer < -1 || rng_producer > 1 || potts_nibbles < -1 || potts_nibbles > 1)
+    return REWL_E_INVAL;
   LaunchPlan pl = c->plan;
   for (int k = 0; k < 3; ++k) {
     if (cls >= 0 && k != cls) continue;
     int rc = plan_class(c->lo, k, lds_budget_bytes(), page_bins, walkers_per_group, rng_producer,
-                        pl.cls[k]);
+                        potts_nibbles, pl.cls[k]);
     if (rc) return rc;
   }
   fill_table(c->lo, pl);
@@ -626,12 +642,16 @@ int rewl_autotune(rewl_ctx* c, int64_t flips, int32_t repeats, int32_t* out) {
     page_range(L, cls, pmin, pmax);
     for (int p = pmin; p <= pmax; p <<= 1) cands.push_back(p);
     float best_ms = -1.0f;
-    std::vector<std::pair<int, int>> shapes;  // (page, producer)
+    struct Shape {
+      int page, prod, nib;
+    };
+    std::vector<Shape> shapes;
     for (int p : cands)
-      for (int prod = 0; prod < 2; ++prod) shapes.push_back({p, prod});
-    for (const auto& shp : shapes) {
+      for (int prod = 0; prod < 2; ++prod)
+        for (int nib = 0; nib < (cls == 2 && L.nib_ok[cls] ? 2 : 1); ++nib) shapes.push_back({p, prod, nib});
+    for (const Shape& shp : shapes) {
       LaunchPlan pl = best;
-      if (plan_class(L, cls, budget, shp.first, 0, shp.second, pl.cls[cls])) continue;
+      if (plan_class(L, cls, budget, shp.page, 0, shp.prod, shp.nib, pl.cls[cls])) continue;
       fill_table(L, pl);
       rc = install_plan(c, pl);
       if (!rc) rc = hip_rc(hipMemcpyAsync(c->ws, snap.data(), c->lo.o_wg, hipMemcpyHostToDevice, c->stream));

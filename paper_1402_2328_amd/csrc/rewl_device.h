@@ -162,6 +162,42 @@ __device__ __forceinline__ bool accept32_flat(uint32_t u, float delta) {
   return (float)u < ldexpf(p, n + 24);
 }
 
+// Fast exact acceptance.  A single-precision estimate e of exp(x), x the
+// clamped delta, from the hardware base-2 exponential of x log2(e) has a
+// relative error below 1e-5: x and log2(e) rounded to float (each < 2^-24
+// relative, |x| <= 40) and the product rounded (< 58 * 2^-24 absolute) shift
+// the exponent by < 1e-5 in total, and the instruction itself is accurate to
+// about one float ulp.  With the slack s = 2^-10, far above that bound, the
+// uniform u = u53 * 2^-53, which lies in [hi 2^-32, (hi + 1) 2^-32), is
+// surely below exp_det(x) when (hi + 1) 2^-32 <= e (1 - s) and surely not
+// when hi 2^-32 >= e (1 + s); only in between (probability about 2 s e per
+// attempt) is accept64_flat evaluated.  The decision is therefore always
+// accept64_flat's.  Comparisons are in FP64 on exact conversions, with the
+// power of two moved onto e.
+__device__ __forceinline__ bool accept64_fast(uint32_t hi, uint32_t lo, double delta) {
+  const double x = fmin(fmax(delta, -40.0), 0.0);
+  const double e = (double)__builtin_amdgcn_exp2f((float)x * 0x1.715476p+0f);
+  const double h = (double)hi;
+  const bool yes = h + 1.0 <= e * ((1.0 - 0x1p-10) * 0x1p32);
+  const bool no = h >= e * ((1.0 + 0x1p-10) * 0x1p32);
+  bool a = yes;
+  if (!yes && !no) a = accept64_flat(hi, lo, delta);
+  return a;
+}
+
+// The same pre-test for the 24-bit uniform u of accept32_flat (u lies in
+// [u, u + 1) 2^-24 exactly).
+__device__ __forceinline__ bool accept32_fast(uint32_t u, float delta) {
+  const float x = fminf(fmaxf(delta, -17.0f), 0.0f);
+  const double e = (double)__builtin_amdgcn_exp2f(x * 0x1.715476p+0f);
+  const double h = (double)u;
+  const bool yes = h + 1.0 <= e * ((1.0 - 0x1p-10) * 0x1p24);
+  const bool no = h >= e * ((1.0 + 0x1p-10) * 0x1p24);
+  bool a = yes;
+  if (!yes && !no) a = accept32_flat(u, delta);
+  return a;
+}
+
 // ---- two-float arithmetic (Knuth's TwoSum, Dekker's FastTwoSum) ----
 __device__ __forceinline__ void df_add1(float ah, float al, float b, float& rh, float& rl) {
   const float s = ah + b;

@@ -95,9 +95,10 @@ struct DevPtrs {
 
 // Launch shape of one sweep kernel class (Ising L <= 32, Ising L <= 64,
 // Potts): lanes per LDS row (walkers per workgroup), 32-bit lattice words
-// per lane, ln g / H page rows per lane, first workgroup in the table.
+// per lane, ln g / H page rows per lane, first workgroup in the table, and
+// for Potts whether spins are kept as 4-bit nibbles (else bytes).
 struct SweepShape {
-  int32_t stride, nw, page, wg_offset;
+  int32_t stride, nw, page, wg_offset, nib;
 };
 
 // Launchers (kernels TU).  All enqueue on `s` and return the launch status.

@@ -22,6 +22,8 @@
 // depend on the walker-to-lane mapping, page size or launch shape.
 #include <math.h>
 
+#include <type_traits>
+
 #include "rewl_device.h"
 #include "rewl_internal.h"
 
@@ -73,6 +75,7 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
   const int64_t nchunks = (flips + kRngChunk - 1) / kRngChunk;
   uint32_t* lat = reinterpret_cast<uint32_t*>(lds);                           // [NWL][S]
   unsigned char* latb = lds;                                                   // byte view (Potts)
+  // Potts spins: 4-bit nibbles (8 per word; every q <= 16) or bytes
   unsigned char* pg = lds + (size_t)4 * NWL * S;
   double* plg = reinterpret_cast<double*>(pg);                                 // [PG][S] FP64
   float* plh = reinterpret_cast<float*>(pg);                                   // [PG][S] FP32C hi
@@ -80,6 +83,7 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
   uint32_t* pH = reinterpret_cast<uint32_t*>(pg + (size_t)8 * PG * S);         // [PG][S]
 
   const int L = Ig.L, N = Ig.N, q = Ig.q, bshift = Ig.binw_shift;
+  const bool nib = MODEL == kPotts && sh.nib != 0;
   const float invL = Ig.invL;
   const uint32_t k0 = Ig.key0, k1 = Ig.key1;
   const uint32_t tagw = kTagMC | ((uint32_t)Ig.inst << 8);
@@ -160,6 +164,12 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
         lat[(y * ROWW + part) * S + lane] = word;
       }
     }
+  } else if (nib) {
+    for (int i = 0; i < ((N + 7) >> 3); ++i) {
+      uint32_t word = 0;
+      for (int b = 0; b < 8 && 8 * i + b < N; ++b) word |= (uint32_t)(uint8_t)gsp[8 * i + b] << (4 * b);
+      lat[i * S + lane] = word;
+    }
   } else {
     const uint32_t* src = reinterpret_cast<const uint32_t*>(gsp);
     const int nwi = (N + 3) >> 2;
@@ -212,7 +222,9 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
   const int S4 = S * 4;
   // addresses stay below 2^24, so 24-bit multiplies (full rate) suffice
   auto pbyte = [&](int site) { return __mul24(site >> 2, S4) + lane4 + (site & 3); };
+
   auto prow = [&](int row) { return __mul24(row, S) + lane; };
+  auto pnib = [&](int site) { return prow(site >> 3); };  // word holding a nibble
 
   // Software pipeline: the Philox block of attempt t+1 (it depends only on
   // the attempt counter) is computed in three slices placed in the latency
@@ -220,13 +232,17 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
   // ln g read is issued, and beside the exponential.  sched_barrier keeps
   // the compiler from hoisting the slices back together.
   // One attempt with Philox block r; without a producer it also computes
-  // rn, the block of the next attempt, in slices.
-  auto attempt = [&](const uint4 r, uint4& rn) {
+  // rn, the block of the next attempt, in slices.  P2 (L a power of two) and
+  // NB (Potts nibbles) are compile-time copies of the loop, chosen once per
+  // launch, so that no branch splits the attempt's scheduling region.
+  auto attempt = [&](const uint4 r, uint4& rn, auto p2t, auto nbt) {
+    constexpr bool P2 = decltype(p2t)::value;
+    constexpr bool NB = decltype(nbt)::value;
     const uint64_t an = att + 1;
     const uint4 cn = make_uint4((uint32_t)an, (uint32_t)(an >> 32), (uint32_t)loc, tagw);
     const int site = (int)__umulhi(r.x, (uint32_t)N);
     int y, x, xr, xl, yd, yu;
-    if (pow2) {  // uniform: shifts and masks
+    if constexpr (P2) {  // shifts and masks
       y = site >> lgL;
       x = site & Lm;
       xr = (x + 1) & Lm;
@@ -288,11 +304,23 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
       dE = 4 * db;
     } else {
       const int rowy = __mul24(y, L);
-      const int s0 = (int)latb[pbyte(site)];
-      const int a = (int)latb[pbyte(rowy + xr)];
-      const int b = (int)latb[pbyte(rowy + xl)];
-      const int c = (int)latb[pbyte(__mul24(yd, L) + x)];
-      const int d = (int)latb[pbyte(__mul24(yu, L) + x)];
+      int s0, a, b, c, d;
+      if constexpr (NB) {
+        const int sa = rowy + xr, sb = rowy + xl, sc = __mul24(yd, L) + x, sd = __mul24(yu, L) + x;
+        widx = pnib(site);
+        wrow = lat[widx];
+        s0 = (int)__builtin_amdgcn_ubfe(wrow, (site & 7) * 4, 4);
+        a = (int)__builtin_amdgcn_ubfe(lat[pnib(sa)], (sa & 7) * 4, 4);
+        b = (int)__builtin_amdgcn_ubfe(lat[pnib(sb)], (sb & 7) * 4, 4);
+        c = (int)__builtin_amdgcn_ubfe(lat[pnib(sc)], (sc & 7) * 4, 4);
+        d = (int)__builtin_amdgcn_ubfe(lat[pnib(sd)], (sd & 7) * 4, 4);
+      } else {
+        s0 = (int)latb[pbyte(site)];
+        a = (int)latb[pbyte(rowy + xr)];
+        b = (int)latb[pbyte(rowy + xl)];
+        c = (int)latb[pbyte(__mul24(yd, L) + x)];
+        d = (int)latb[pbyte(__mul24(yu, L) + x)];
+      }
       __builtin_amdgcn_sched_barrier(0);
       if constexpr (!PROD) {
         rn = philox_rounds<0, 4>(cn, k0, k1);
@@ -318,7 +346,7 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
         REWL_PIN4(rn);
       }
       __builtin_amdgcn_sched_barrier(0);
-      const bool a = accept64_flat(r.z, r.w, lcur - ln);
+      const bool a = accept64_fast(r.z, r.w, lcur - ln);
       if constexpr (!PROD) {
         rn = philox_rounds<7, 10>(rn, k0, k1);
         REWL_PIN4(rn);
@@ -334,7 +362,7 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
         REWL_PIN4(rn);
       }
       __builtin_amdgcn_sched_barrier(0);
-      const bool a = accept32_flat(r.z >> 8, (hcur - nh) + (lcur_lo - nl));
+      const bool a = accept32_fast(r.z >> 8, (hcur - nh) + (lcur_lo - nl));
       if constexpr (!PROD) {
         rn = philox_rounds<7, 10>(rn, k0, k1);
         REWL_PIN4(rn);
@@ -347,7 +375,12 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
       if (MODEL == kIsing) {
         lat[widx] = wrow ^ (1u << (x & 31));
       } else {
-        latb[pbyte(site)] = (unsigned char)nv;
+        if constexpr (NB) {
+          const int sh4 = (site & 7) * 4;
+          lat[widx] = (wrow & ~(15u << sh4)) | ((uint32_t)nv << sh4);
+        } else {
+          latb[pbyte(site)] = (unsigned char)nv;
+        }
       }
       E += dE;
       bin = bn;
@@ -420,27 +453,38 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
     ++att;
   };
 
-  if constexpr (!PROD) {
-    uint4 r = philox10(make_uint4((uint32_t)att, (uint32_t)(att >> 32), (uint32_t)loc, tagw), k0, k1);
-    for (int64_t t = 0; t < flips; ++t) {
-      uint4 rn;
-      attempt(r, rn);
-      r = rn;
-    }
-  } else {
-    __syncthreads();  // chunk 0 is in the buffer
-    for (int64_t c = 0; c < nchunks; ++c) {
-      const uint4* src = rbuf + (size_t)(c & 1) * kRngChunk * S + lane;
-      const int n = (flips - c * kRngChunk) < kRngChunk ? (int)(flips - c * kRngChunk) : kRngChunk;
-      uint4 r = src[0];
-      for (int i = 0; i < n; ++i) {
-        const uint4 rnext = src[(size_t)(i + 1 < n ? i + 1 : i) * S];
-        uint4 unused;
-        attempt(r, unused);
-        r = rnext;
+  auto run = [&](auto p2t, auto nbt) {
+    if constexpr (!PROD) {
+      uint4 r = philox10(make_uint4((uint32_t)att, (uint32_t)(att >> 32), (uint32_t)loc, tagw), k0, k1);
+      for (int64_t t = 0; t < flips; ++t) {
+        uint4 rn;
+        attempt(r, rn, p2t, nbt);
+        r = rn;
       }
-      __syncthreads();  // chunk c consumed, chunk c + 1 written
+    } else {
+      __syncthreads();  // chunk 0 is in the buffer
+      for (int64_t c = 0; c < nchunks; ++c) {
+        const uint4* src = rbuf + (size_t)(c & 1) * kRngChunk * S + lane;
+        const int n = (flips - c * kRngChunk) < kRngChunk ? (int)(flips - c * kRngChunk) : kRngChunk;
+        uint4 r = src[0];
+        for (int i = 0; i < n; ++i) {
+          const uint4 rnext = src[(size_t)(i + 1 < n ? i + 1 : i) * S];
+          uint4 unused;
+          attempt(r, unused, p2t, nbt);
+          r = rnext;
+        }
+        __syncthreads();  // chunk c consumed, chunk c + 1 written
+      }
     }
+  };
+  using T = std::true_type;
+  using F = std::false_type;
+  if (MODEL == kPotts && nib) {
+    if (pow2) run(T{}, T{});
+    else run(F{}, T{});
+  } else {
+    if (pow2) run(T{}, F{});
+    else run(F{}, F{});
   }
 
   // ---- stage out ----
@@ -480,6 +524,11 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
         const int xe = (L - x0) < 32 ? (L - x0) : 32;
         for (int b = 0; b < xe; ++b) gsp[y * L + x0 + b] = ((word >> b) & 1) ? 1 : -1;
       }
+    }
+  } else if (nib) {
+    for (int i = 0; i < ((N + 7) >> 3); ++i) {
+      const uint32_t word = lat[i * S + lane];
+      for (int b = 0; b < 8 && 8 * i + b < N; ++b) gsp[8 * i + b] = (int8_t)((word >> (4 * b)) & 15);
     }
   } else {
     uint32_t* dst = reinterpret_cast<uint32_t*>(gsp);

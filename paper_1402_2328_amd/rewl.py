@@ -69,7 +69,7 @@ def lib():
     L.rewl_workspace_bytes.argtypes = [P, I32, P, P]
     L.rewl_init.argtypes = [P, I32, P, P, P, SZ, P, C.POINTER(C.c_void_p)]
     L.rewl_run_sweeps.argtypes = [P, I64]
-    L.rewl_set_launch.argtypes = [P, I32, I32, I32, I32, P]
+    L.rewl_set_launch.argtypes = [P, I32, I32, I32, I32, I32, P]
     L.rewl_autotune.argtypes = [P, I64, I32, P]
     L.rewl_merge.argtypes = [P]
     L.rewl_exchange.argtypes = [P]
@@ -189,20 +189,22 @@ class Context:
     def _plan(out):
         plan = {}
         for c, name in enumerate(Context.CLASSES):
-            if out[5 * c + 3] > 0:
-                plan[name] = {"page_bins": int(out[5 * c]), "walkers_per_group": int(out[5 * c + 1]),
-                              "lds_bytes": int(out[5 * c + 2]), "workgroups": int(out[5 * c + 3]),
-                              "rng_producer": int(out[5 * c + 4])}
+            if out[6 * c + 3] > 0:
+                plan[name] = {"page_bins": int(out[6 * c]), "walkers_per_group": int(out[6 * c + 1]),
+                              "lds_bytes": int(out[6 * c + 2]), "workgroups": int(out[6 * c + 3]),
+                              "rng_producer": int(out[6 * c + 4]), "potts_nibbles": int(out[6 * c + 5])}
         return plan
 
-    def set_launch(self, page_bins=0, walkers_per_group=0, cls=-1, rng_producer=-1):
-        out = np.zeros(15, np.int32)
+    def set_launch(self, page_bins=0, walkers_per_group=0, cls=-1, rng_producer=-1,
+                   potts_nibbles=-1):
+        out = np.zeros(18, np.int32)
         _check(lib().rewl_set_launch(self._h, int(cls), int(page_bins), int(walkers_per_group),
-                                     int(rng_producer), _p(out)), "rewl_set_launch")
+                                     int(rng_producer), int(potts_nibbles), _p(out)),
+               "rewl_set_launch")
         return self._plan(out)
 
     def autotune(self, flips, repeats=1):
-        out = np.zeros(15, np.int32)
+        out = np.zeros(18, np.int32)
         _check(lib().rewl_autotune(self._h, int(flips), int(repeats), _p(out)), "rewl_autotune")
         return self._plan(out)
 

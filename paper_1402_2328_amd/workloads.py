@@ -35,7 +35,7 @@ def bench_replicas(cfg, n_cu=256):
     workgroups once, for the default launch plan."""
     from . import rewl
     ctx = rewl.Context([rewl_params_of(cfg)])
-    (plan,) = ctx.set_launch(rng_producer=0).values()
+    (plan,) = ctx.set_launch(rng_producer=0, potts_nibbles=1).values()
     ctx.close()
     per_cu = max(1, (160 * 1024) // plan["lds_bytes"])
     return max(1, (n_cu * per_cu) // plan["workgroups"])

@@ -33,6 +33,9 @@ SMALL = {
                                    flips=700, seed=5),
     "potts_q3_L10_h6_m3": WL.config(WL.POTTS, 10, q=3, n_windows=6, walkers_per_window=3,
                                     flips=900, seed=6),
+    # q > 16: Potts spins kept as bytes rather than nibbles in LDS
+    "potts_q20_L7_h3_m2": WL.config(WL.POTTS, 7, q=20, n_windows=3, walkers_per_window=2,
+                                    flips=600, seed=13),
     "ising_L8_fp32c": WL.config(WL.ISING, 8, n_windows=4, walkers_per_window=2, lnf_final=1e-6,
                                 flips=500, seed=3, precision=WL.FP32C),
     "potts_q10_L8_fp32c": WL.config(WL.POTTS, 8, q=10, n_windows=4, walkers_per_window=4,
@@ -211,23 +214,30 @@ def test_unreachable_window_is_reported_on_both_sides():
     assert ctx.running() == 0
 
 
-@pytest.mark.parametrize("name,page,group,prod", [("ising_L16_h5_m4", 16, 0, 0), ("ising_L16_h5_m4", 0, 5, 1),
-                                                  ("ising_L16_h5_m4", 64, 0, 1),
-                                                  ("potts_q5_L12_h9_m7_ragged", 32, 13, 1),
-                                                  ("potts_q10_L8_h4_m4", 32, 3, 0),
-                                                  ("ising_L40_h6_m2_tworow", 16, 0, 1),
-                                                  ("ising_L8_fp32c", 16, 0, 1),
-                                                  ("potts_q10_L8_fp32c", 32, 7, 0)])
-def test_page_size_and_group_shape_do_not_change_results(name, page, group, prod):
+@pytest.mark.parametrize("name,page,group,prod,nib", [
+    ("ising_L16_h5_m4", 16, 0, 0, -1), ("ising_L16_h5_m4", 0, 5, 1, -1),
+    ("ising_L16_h5_m4", 64, 0, 1, -1),
+    ("potts_q5_L12_h9_m7_ragged", 32, 13, 1, 1), ("potts_q5_L12_h9_m7_ragged", 64, 0, 0, 0),
+    ("potts_q10_L8_h4_m4", 32, 3, 0, 1),
+    ("potts_q20_L7_h3_m2", 32, 0, 0, 1),
+    ("ising_L40_h6_m2_tworow", 16, 0, 1, -1),
+    ("ising_L8_fp32c", 16, 0, 1, -1),
+    ("potts_q10_L8_fp32c", 32, 7, 0, 1), ("potts_q10_L8_fp32c", 32, 0, 1, 0)])
+def test_page_size_and_group_shape_do_not_change_results(name, page, group, prod, nib):
     """Pages much smaller than the windows make the page follow the walker
     through device memory at almost every move; with prod = 1 a second
-    wavefront supplies the random numbers.  Results must not change."""
+    wavefront supplies the random numbers; nib picks the Potts lattice
+    format (nibbles need q <= 16, so q = 20 keeps bytes).  Results must not
+    change."""
     cfg = SMALL[name]
     ctx = gpu_context([cfg])
-    plan = ctx.set_launch(page_bins=page, walkers_per_group=group, rng_producer=prod)
+    plan = ctx.set_launch(page_bins=page, walkers_per_group=group, rng_producer=prod,
+                          potts_nibbles=nib)
     print(f"[parity] {name}: plan {plan}", flush=True)
     (p,) = plan.values()
     assert p["page_bins"] & (p["page_bins"] - 1) == 0 and p["rng_producer"] == prod
+    if nib >= 0 and cfg["model"] == WL.POTTS:
+        assert p["potts_nibbles"] == (nib if cfg["q"] <= 16 else 0)
     if page:
         assert p["page_bins"] == page
     sim = oracle_sim(cfg)
