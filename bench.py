@@ -80,6 +80,7 @@ def parse():
     ap.add_argument("--schedule", choices=["halving", "1t"], default="halving")
     ap.add_argument("--speedup", action="store_true")
     ap.add_argument("--L", type=int, default=32, help="lattice size (--speedup)")
+    ap.add_argument("--q", type=int, default=2, help="--speedup: q > 2 runs q-state Potts")
     ap.add_argument("--hs", default="1,2,4,8,16,32", help="window counts (--speedup)")
     ap.add_argument("--walkers", type=int, default=None,
                     help="walkers per window (--speedup: default 1; --converge: the config's)")
@@ -275,8 +276,9 @@ def converge(a):
 def speedup(a):
     """Speed-up s_o(h, m) = N_single / N_o(h, m) (Eq. for the speed-up in
     Sec. 4): N is the number of MC steps per walker the slowest window needs
-    to finish its first WL iteration.  Ising L x L (default 32), m walkers
-    per window, overlap 75 %, exchange every F flips.  Every h runs as R
+    to finish its first WL iteration.  Ising L x L (default 32), or
+    q-state Potts with --q, m walkers per window, overlap 75 %, exchange
+    every F flips.  Every h runs as R
     independent instances in one batched context; N(h) is their median.
     Then the run-time balanced split (Fig. 1b) is planned per h from the
     equal-split runs (rewl_balanced_windows on the mean per-window first
@@ -287,7 +289,9 @@ def speedup(a):
     from paper_1402_2328_amd import workloads as WL
     hs = [int(x) for x in a.hs.split(",")]
     R, F, m = a.replicas, a.flips, (a.walkers or 1)
-    base = WL.config(WL.ISING, a.L, n_windows=1, walkers_per_window=m, lnf_final=0.5, flips=F)
+    model = WL.POTTS if a.q > 2 else WL.ISING
+    base = WL.config(model, a.L, q=a.q, n_windows=1, walkers_per_window=m, lnf_final=0.5, flips=F)
+    what = f"2D q={a.q} Potts L={a.L}" if model == WL.POTTS else f"2D Ising L={a.L}"
 
     def measure(tag, split, seed0):
         cfgs, windows = [], []
@@ -350,7 +354,7 @@ def speedup(a):
         return out, slope
 
     out = {"metric": "speed-up s(h) = N_single / N_slowest(h), first WL iteration",
-           "config": {"workload": f"2D Ising L={a.L}, m={m} walkers/window, overlap 75%, "
+           "config": {"workload": f"{what}, m={m} walkers/window, overlap 75%, "
                                   f"F={F} flips per exchange, flatness 0.8, {R} instances per h",
                       "hs": hs, "alpha": a.alpha}}
     for name, res, t in (("equal", eq, t_eq), ("balanced", bal, t_bal), ("balanced_refined", ref, t_ref)):
