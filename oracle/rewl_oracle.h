@@ -21,10 +21,13 @@
  *   Sec. 3, joining: beta = d log g / dE, join where |beta_i - beta_j| is
  *           smallest, rescale g_j at E_join, piecewise Eq. (2); 5-point
  *           derivative stencil (Fig. 2 caption).
+ *   Sec. 2, the "1/t" rule named as compatible with REWL: ln f halves while
+ *           every walker visits every level, then follows 1/t.
+ *   Sec. 3, statistical errors by the jackknife over the m pieces per window.
  *   Sec. 5, Eqs. (5)-(6): <E>, C_V from g(E).
- * Points the paper leaves open are fixed by the readings listed in the
- * project design notes (window edges, RNG streams, warm-up, flatness mask,
- * merge order, exchange pairing, normalisation).
+ * Points the paper leaves open (window edges, RNG streams, warm-up,
+ * flatness mask, merge order, exchange pairing, normalisation) are fixed
+ * where each is implemented, and the comments there state the choice.
  *
  * Error convention: functions returning int give 0 on success and a negative
  * value on error; orc_new returns NULL on invalid parameters.
