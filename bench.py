@@ -11,7 +11,9 @@ by rewl_autotune before timing (untimed; it restores the state it touched).
 
 Printed: one JSON line with spin-flip attempts/s, the sweep kernel's
 roofline position (kernel time from HIP events recorded on the library's
-stream) and the single-threaded CPU oracle's attempts/s on a bounded sample.
+stream), the time to converge of 8 Ising L=8 instances with their error
+against the exact density of states (after the timed region), and the
+single-threaded CPU oracle's attempts/s on a bounded sample.
 
 --workload cfg3 (q=10 Potts L=20, filled with copies) or mix (the batched
 64-instance mix) measures the other forms; --precision fp32c the two-float
@@ -29,6 +31,7 @@ tests/converge_report.py.
 import argparse
 import hashlib
 import json
+import math
 import os
 import platform
 import sys
@@ -74,6 +77,8 @@ def parse():
                     help="fixed ln g page size for the sweep (0: autotune)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-ttc", action="store_true",
+                    help="skip the time-to-converge run (Ising L=8) after the throughput run")
     ap.add_argument("--converge", action="store_true")
     ap.add_argument("--config", choices=["cfg1", "cfg2", "cfg3", "cfg34"], default="cfg2")
     ap.add_argument("--max-minutes", type=float, default=50.0)
@@ -133,7 +138,7 @@ def traffic_from_profile(R, flips, page):
     return (prof["fetch_kib"] * prof["fetch_scale"] + prof["write_kib"] * prof["write_scale"]) * 1024
 
 
-def run_to_convergence(ctx, R, flips, max_s, tag):
+def run_to_convergence(ctx, R, flips, max_s, tag, quiet=False):
     """Cycles until every instance is finished (or max_s); returns the wall
     time at which each instance finished."""
     import torch
@@ -149,13 +154,43 @@ def run_to_convergence(ctx, R, flips, max_s, tag):
         for i, s in enumerate(st):
             if s["done"] and i not in done_at:
                 done_at[i] = now
-        if cycles % 1000 == 0 or len(done_at) == R:
+        if not quiet and (cycles % 1000 == 0 or len(done_at) == R):
             stages = np.array([s["stage"].min() for s in st])
             print(json.dumps({"run": tag, "cycles": cycles, "t": round(now, 1), "done": len(done_at),
                               "stage_min": int(stages.min()),
                               "stage_med": float(np.median(stages))}), flush=True)
         if len(done_at) == R or now > max_s:
             return done_at, cycles, now
+
+
+def exact_ising_lng(L):
+    """ln g(E) of the periodic L x L Ising model, E = -2N + 4k, from the
+    stored exact table (tests/golden, Kaufman's closed form)."""
+    path = os.path.join(ROOT, "tests", "golden", f"ising_dos_L{L}.txt")
+    vals = [int(x) for x in open(path) if not x.startswith("#")]
+    return np.array([math.log(v) if v else -np.inf for v in vals])
+
+
+def time_to_converge_cfg1(R=8):
+    """Ising L=8 REWL (4 windows x 1 walker, halving to ln f = 1e-6, F=1000)
+    run R times to convergence: wall time per instance and its max |ln g
+    error| against the exact density of states."""
+    from paper_1402_2328_amd import rewl
+    from paper_1402_2328_amd import workloads as WL
+    cfg = WL.CFG1
+    F = cfg["flips_per_exchange"]
+    ctx = rewl.Context([WL.rewl_params_of(cfg)] * R)
+    ctx.autotune(F)
+    done_at, cycles, wall = run_to_convergence(ctx, R, F, 120, "cfg1", quiet=True)
+    exact = exact_ising_lng(cfg["L"])
+    fin = np.isfinite(exact)
+    errs = [float(np.max(np.abs(ctx.get_lng(i)[0][fin] - exact[fin]))) for i in sorted(done_at)]
+    ctx.close()
+    return {"config": "Ising L=8, 4 windows x 1 walker, ln f 1 -> 1e-6 by halving, F=1000",
+            "instances": R, "finished": len(done_at),
+            "wall_s_median": float(np.median(list(done_at.values()))) if done_at else None,
+            "wall_s_all": wall, "max_abs_err_vs_exact": errs,
+            "max_abs_err_median": float(np.median(errs)) if errs else None}
 
 
 def cv_peak(ctx, i, T):
@@ -468,6 +503,8 @@ def main():
         # the algorithmic slot count above is that of the FP64 Ising attempt
         out["roofline"] = None
         out["kernel_ms"] = sweep_ms
+    if a.workload == "cfg2" and prec == WL.FP64 and not a.no_ttc:
+        out["time_to_converge"] = time_to_converge_cfg1()
     if not a.no_cpu and a.workload == "cfg2":
         out["cpu_baseline"] = cpu_baseline(a.flips, a.cpu_seconds)
     print(json.dumps(out), flush=True)
