@@ -226,114 +226,13 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
   auto prow = [&](int row) { return __mul24(row, S) + lane; };
   auto pnib = [&](int site) { return prow(site >> 3); };  // word holding a nibble
 
-  // Software pipeline: the Philox block of attempt t+1 (it depends only on
-  // the attempt counter) is computed in three slices placed in the latency
-  // shadows of attempt t -- after the lattice reads are issued, after the
-  // ln g read is issued, and beside the exponential.  sched_barrier keeps
-  // the compiler from hoisting the slices back together.
-  // One attempt with Philox block r; without a producer it also computes
-  // rn, the block of the next attempt, in slices.  P2 (L a power of two) and
-  // NB (Potts nibbles) are compile-time copies of the loop, chosen once per
-  // launch, so that no branch splits the attempt's scheduling region.
-  auto attempt = [&](const uint4 r, uint4& rn, auto p2t, auto nbt) {
-    constexpr bool P2 = decltype(p2t)::value;
+  // Rest of an attempt once the proposal is known: ln g at the proposed
+  // bin, acceptance, lattice and ln g / H update, page follow.  Without a
+  // producer, the last two Philox slices of the block in flight (rn) are
+  // placed beside the ln g read and the exponential.
+  auto complete = [&](const uint4 r, uint4& rn, int dE, int db, int nv, int widx, uint32_t wrow,
+                      int x, int site, auto nbt) -> bool {
     constexpr bool NB = decltype(nbt)::value;
-    const uint64_t an = att + 1;
-    const uint4 cn = make_uint4((uint32_t)an, (uint32_t)(an >> 32), (uint32_t)loc, tagw);
-    const int site = (int)__umulhi(r.x, (uint32_t)N);
-    int y, x, xr, xl, yd, yu;
-    if constexpr (P2) {  // shifts and masks
-      y = site >> lgL;
-      x = site & Lm;
-      xr = (x + 1) & Lm;
-      xl = (x - 1) & Lm;
-      yd = (y + 1) & Lm;
-      yu = (y - 1) & Lm;
-    } else {
-      y = (int)(((float)site + 0.5f) * invL);
-      x = site - __mul24(y, L);
-      xr = (x + 1 == L) ? 0 : x + 1;
-      xl = (x == 0) ? L - 1 : x - 1;
-      yd = (y + 1 == L) ? 0 : y + 1;
-      yu = (y == 0) ? L - 1 : y - 1;
-    }
-    int dE, db, nv = 0;
-    int widx = 0;
-    uint32_t wrow = 0;
-    if (MODEL == kIsing) {
-      // bit b of a row word: spin at x = 32 * part + b is +1
-      int s0, a, b, c, d;
-      if (ROWW == 1) {
-        widx = prow(y);
-        wrow = lat[widx];
-        const uint32_t wu = lat[prow(yu)];
-        const uint32_t wd = lat[prow(yd)];
-        __builtin_amdgcn_sched_barrier(0);
-        if constexpr (!PROD) {
-          rn = philox_rounds<0, 4>(cn, k0, k1);
-          REWL_PIN4(rn);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        s0 = (wrow >> x) & 1;
-        a = (wrow >> xr) & 1;
-        b = (wrow >> xl) & 1;
-        c = (wd >> x) & 1;
-        d = (wu >> x) & 1;
-      } else {
-        const int px = x >> 5;
-        const uint32_t r0 = lat[prow(2 * y)];
-        const uint32_t r1 = lat[prow(2 * y + 1)];
-        const uint32_t wu = lat[prow(2 * yu + px)];
-        const uint32_t wd = lat[prow(2 * yd + px)];
-        __builtin_amdgcn_sched_barrier(0);
-        if constexpr (!PROD) {
-          rn = philox_rounds<0, 4>(cn, k0, k1);
-          REWL_PIN4(rn);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        wrow = px ? r1 : r0;
-        s0 = (wrow >> (x & 31)) & 1;
-        a = (((xr >> 5) ? r1 : r0) >> (xr & 31)) & 1;
-        b = (((xl >> 5) ? r1 : r0) >> (xl & 31)) & 1;
-        c = (wd >> (x & 31)) & 1;
-        d = (wu >> (x & 31)) & 1;
-        widx = prow(2 * y + px);
-      }
-      // sigma = 2 bit - 1: dE = 2 s0 (sum of neighbours), bin step dE / 4
-      db = (2 * s0 - 1) * (a + b + c + d - 2);
-      dE = 4 * db;
-    } else {
-      const int rowy = __mul24(y, L);
-      int s0, a, b, c, d;
-      if constexpr (NB) {
-        const int sa = rowy + xr, sb = rowy + xl, sc = __mul24(yd, L) + x, sd = __mul24(yu, L) + x;
-        widx = pnib(site);
-        wrow = lat[widx];
-        s0 = (int)__builtin_amdgcn_ubfe(wrow, (site & 7) * 4, 4);
-        a = (int)__builtin_amdgcn_ubfe(lat[pnib(sa)], (sa & 7) * 4, 4);
-        b = (int)__builtin_amdgcn_ubfe(lat[pnib(sb)], (sb & 7) * 4, 4);
-        c = (int)__builtin_amdgcn_ubfe(lat[pnib(sc)], (sc & 7) * 4, 4);
-        d = (int)__builtin_amdgcn_ubfe(lat[pnib(sd)], (sd & 7) * 4, 4);
-      } else {
-        s0 = (int)latb[pbyte(site)];
-        a = (int)latb[pbyte(rowy + xr)];
-        b = (int)latb[pbyte(rowy + xl)];
-        c = (int)latb[pbyte(__mul24(yd, L) + x)];
-        d = (int)latb[pbyte(__mul24(yu, L) + x)];
-      }
-      __builtin_amdgcn_sched_barrier(0);
-      if constexpr (!PROD) {
-        rn = philox_rounds<0, 4>(cn, k0, k1);
-        REWL_PIN4(rn);
-      }
-      __builtin_amdgcn_sched_barrier(0);
-      int v = s0 + 1 + (int)__umulhi(r.y, (uint32_t)(q - 1));
-      v = (v >= q) ? v - q : v;
-      nv = v;
-      dE = ((a == s0) + (b == s0) + (c == s0) + (d == s0)) -
-           ((a == v) + (b == v) + (c == v) + (d == v));
-      db = dE >> bshift;
-    }
     const int bn = bin + db;
     const bool inwin = (bn >= lo) && (bn <= hi);
     const int jn = inwin ? prow(bn & PM) : jcur;
@@ -449,9 +348,125 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
         pend_n = shn;
       }
     }
-    (void)cn;
     ++att;
+    return acc;
   };
+
+  // Software pipeline: the Philox block of attempt t+1 (it depends only on
+  // the attempt counter) is computed in three slices placed in the latency
+  // shadows of attempt t -- after the lattice reads are issued, after the
+  // ln g read is issued, and beside the exponential.  sched_barrier keeps
+  // the compiler from hoisting the slices back together.
+  // One attempt with Philox block r; without a producer it also computes
+  // rn, the block of the next attempt, in slices.  P2 (L a power of two) and
+  // NB (Potts nibbles) are compile-time copies of the loop, chosen once per
+  // launch, so that no branch splits the attempt's scheduling region.
+  auto attempt = [&](const uint4 r, uint4& rn, auto p2t, auto nbt) {
+    constexpr bool P2 = decltype(p2t)::value;
+    constexpr bool NB = decltype(nbt)::value;
+    const uint64_t an = att + 1;
+    const uint4 cn = make_uint4((uint32_t)an, (uint32_t)(an >> 32), (uint32_t)loc, tagw);
+    const int site = (int)__umulhi(r.x, (uint32_t)N);
+    int y, x, xr, xl, yd, yu;
+    if constexpr (P2) {  // shifts and masks
+      y = site >> lgL;
+      x = site & Lm;
+      xr = (x + 1) & Lm;
+      xl = (x - 1) & Lm;
+      yd = (y + 1) & Lm;
+      yu = (y - 1) & Lm;
+    } else {
+      y = (int)(((float)site + 0.5f) * invL);
+      x = site - __mul24(y, L);
+      xr = (x + 1 == L) ? 0 : x + 1;
+      xl = (x == 0) ? L - 1 : x - 1;
+      yd = (y + 1 == L) ? 0 : y + 1;
+      yu = (y == 0) ? L - 1 : y - 1;
+    }
+    int dE, db, nv = 0;
+    int widx = 0;
+    uint32_t wrow = 0;
+    if (MODEL == kIsing) {
+      // bit b of a row word: spin at x = 32 * part + b is +1
+      int s0, a, b, c, d;
+      if (ROWW == 1) {
+        widx = prow(y);
+        wrow = lat[widx];
+        const uint32_t wu = lat[prow(yu)];
+        const uint32_t wd = lat[prow(yd)];
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (!PROD) {
+          rn = philox_rounds<0, 4>(cn, k0, k1);
+          REWL_PIN4(rn);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        s0 = (wrow >> x) & 1;
+        a = (wrow >> xr) & 1;
+        b = (wrow >> xl) & 1;
+        c = (wd >> x) & 1;
+        d = (wu >> x) & 1;
+      } else {
+        const int px = x >> 5;
+        const uint32_t r0 = lat[prow(2 * y)];
+        const uint32_t r1 = lat[prow(2 * y + 1)];
+        const uint32_t wu = lat[prow(2 * yu + px)];
+        const uint32_t wd = lat[prow(2 * yd + px)];
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (!PROD) {
+          rn = philox_rounds<0, 4>(cn, k0, k1);
+          REWL_PIN4(rn);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        wrow = px ? r1 : r0;
+        s0 = (wrow >> (x & 31)) & 1;
+        a = (((xr >> 5) ? r1 : r0) >> (xr & 31)) & 1;
+        b = (((xl >> 5) ? r1 : r0) >> (xl & 31)) & 1;
+        c = (wd >> (x & 31)) & 1;
+        d = (wu >> (x & 31)) & 1;
+        widx = prow(2 * y + px);
+      }
+      // sigma = 2 bit - 1: dE = 2 s0 (sum of neighbours), bin step dE / 4
+      db = (2 * s0 - 1) * (a + b + c + d - 2);
+      dE = 4 * db;
+    } else {
+      const int rowy = __mul24(y, L);
+      int s0, a, b, c, d;
+      if constexpr (NB) {
+        const int sa = rowy + xr, sb = rowy + xl, sc = __mul24(yd, L) + x, sd = __mul24(yu, L) + x;
+        widx = pnib(site);
+        wrow = lat[widx];
+        s0 = (int)__builtin_amdgcn_ubfe(wrow, (site & 7) * 4, 4);
+        a = (int)__builtin_amdgcn_ubfe(lat[pnib(sa)], (sa & 7) * 4, 4);
+        b = (int)__builtin_amdgcn_ubfe(lat[pnib(sb)], (sb & 7) * 4, 4);
+        c = (int)__builtin_amdgcn_ubfe(lat[pnib(sc)], (sc & 7) * 4, 4);
+        d = (int)__builtin_amdgcn_ubfe(lat[pnib(sd)], (sd & 7) * 4, 4);
+      } else {
+        s0 = (int)latb[pbyte(site)];
+        a = (int)latb[pbyte(rowy + xr)];
+        b = (int)latb[pbyte(rowy + xl)];
+        c = (int)latb[pbyte(__mul24(yd, L) + x)];
+        d = (int)latb[pbyte(__mul24(yu, L) + x)];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (!PROD) {
+        rn = philox_rounds<0, 4>(cn, k0, k1);
+        REWL_PIN4(rn);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      int v = s0 + 1 + (int)__umulhi(r.y, (uint32_t)(q - 1));
+      v = (v >= q) ? v - q : v;
+      nv = v;
+      dE = ((a == s0) + (b == s0) + (c == s0) + (d == s0)) -
+           ((a == v) + (b == v) + (c == v) + (d == v));
+      db = dE >> bshift;
+    }
+    complete(r, rn, dE, db, nv, widx, wrow, x, site, nbt);
+    (void)cn;
+  };
+
+
+  using T = std::true_type;
+  using F = std::false_type;
 
   auto run = [&](auto p2t, auto nbt) {
     if constexpr (!PROD) {
@@ -477,8 +492,6 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
       }
     }
   };
-  using T = std::true_type;
-  using F = std::false_type;
   if (MODEL == kPotts && nib) {
     if (pow2) run(T{}, T{});
     else run(F{}, T{});

@@ -48,12 +48,16 @@ SMALL = {
 }
 
 
+@pytest.mark.parametrize("prod", [0, 1])
 @pytest.mark.parametrize("name", list(SMALL))
-def test_initial_state_and_segments_match(name):
+def test_initial_state_and_segments_match(name, prod):
+    """Segments of 1, 2, 10 and 40 cycles, with the random numbers made by
+    the walkers' own wavefront (prod = 0) or by a producer wavefront."""
     cfg = SMALL[name]
     ctx = gpu_context([cfg])
+    ctx.set_launch(rng_producer=prod)
     sim = oracle_sim(cfg)
-    print(f"[parity] {name}: init", flush=True)
+    print(f"[parity] {name} prod={prod}: init", flush=True)
     compare_state(ctx, 0, sim)
     F = cfg["flips_per_exchange"]
     for seg in (1, 2, 10, 40):
