@@ -20,7 +20,7 @@ using namespace rewl;
 
 namespace {
 
-constexpr uint64_t kCkptMagic = 0x3130304c5745524bULL;  // "KREWL001"
+constexpr uint64_t kCkptMagic = 0x3230304c5745524bULL;  // "KREWL002"
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
