@@ -77,6 +77,8 @@ def parse():
                     help="fixed ln g page size for the sweep (0: autotune)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--solo", type=int, default=0,
+                    help="--workload mix: also time this many instances alone")
     ap.add_argument("--no-ttc", action="store_true",
                     help="skip the time-to-converge run (Ising L=8) after the throughput run")
     ap.add_argument("--converge", action="store_true")
@@ -191,6 +193,32 @@ def time_to_converge_cfg1(R=8):
             "wall_s_median": float(np.median(list(done_at.values()))) if done_at else None,
             "wall_s_all": wall, "max_abs_err_vs_exact": errs,
             "max_abs_err_median": float(np.median(errs)) if errs else None}
+
+
+def solo_vs_batch(cfgs, n_sample, flips, batch_cycle_s):
+    """Time a cycle of n_sample instances of the batch run alone (each in a
+    context of its own, autotuned like the batch) and compare the sum over
+    the whole batch, estimated from that sample, with the batched cycle."""
+    import torch
+    from paper_1402_2328_amd import rewl
+    from paper_1402_2328_amd import workloads as WL
+    rng = np.random.Generator(np.random.PCG64(11))
+    pick = sorted(rng.choice(len(cfgs), size=min(n_sample, len(cfgs)), replace=False).tolist())
+    solo = []
+    for i in pick:
+        ctx = rewl.Context([WL.rewl_params_of(cfgs[i])])
+        ctx.autotune(flips)
+        ctx.run_cycles(1, flips)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.run_cycles(3, flips)
+        torch.cuda.synchronize()
+        solo.append((time.perf_counter() - t0) / 3)
+        ctx.close()
+    est = float(np.mean(solo)) * len(cfgs)
+    return {"instances_timed_alone": pick, "solo_cycle_s": solo,
+            "sequential_cycle_s_estimate": est, "batched_cycle_s": batch_cycle_s,
+            "speedup": est / batch_cycle_s}
 
 
 def cv_peak(ctx, i, T):
@@ -505,6 +533,8 @@ def main():
         out["kernel_ms"] = sweep_ms
     if a.workload == "cfg2" and prec == WL.FP64 and not a.no_ttc:
         out["time_to_converge"] = time_to_converge_cfg1()
+    if a.workload == "mix" and a.solo > 0:
+        out["batching"] = solo_vs_batch(cfgs, a.solo, a.flips, dt / a.steps)
     if not a.no_cpu and a.workload == "cfg2":
         out["cpu_baseline"] = cpu_baseline(a.flips, a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -36,7 +36,8 @@ def test_strerror_names_codes():
 
 @pytest.mark.parametrize("bad", [dict(L=1), dict(L=65), dict(n_windows=0), dict(walkers_per_window=0),
                                  dict(walkers_per_window=65), dict(flat=(6, 5)), dict(lnf_init=0.0),
-                                 dict(overlap=(4, 4)), dict(n_windows=400)])
+                                 dict(overlap=(4, 4)), dict(n_windows=400), dict(schedule=2),
+                                 dict(schedule=-1), dict(q=128, model=workloads.POTTS)])
 def test_workspace_bytes_rejects_bad_parameters(bad):
     cfg = dict(workloads.CFG1)
     cfg.update(bad)
@@ -65,3 +66,15 @@ def test_explicit_windows_validated():
                 [([0, 40, 41, 42], [37, 46, 55, 64])],       # no overlap between 0 and 1
                 [([0, 9, 9, 27], [37, 46, 55, 64])]):        # not increasing
         assert rewl.rewl_workspace_bytes(p, bad) == 0
+
+
+def test_reserved_parameter_field_must_be_zero():
+    p = workloads.rewl_params_of(workloads.CFG1)
+    assert rewl.rewl_workspace_bytes([p]) > 0
+    p.reserved = 1
+    assert rewl.rewl_workspace_bytes([p]) == 0
+
+
+def test_one_over_t_configs_lay_out():
+    cfg = dict(workloads.CFG2, schedule=workloads.ONE_OVER_T, walkers_per_window=64)
+    assert rewl.rewl_workspace_bytes([workloads.rewl_params_of(cfg)]) > 0
