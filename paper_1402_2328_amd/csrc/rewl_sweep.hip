@@ -126,6 +126,8 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
   const bool frozen = WS.frozen != 0;
   const double lnf = WS.lnf;
   const float lnf32 = (float)WS.lnf;
+  const double lnf_eff = frozen ? 0.0 : lnf;
+  const uint32_t h_inc = frozen ? 0u : 1u;
 
   // The walkers of a workgroup are consecutive slots of one instance, so
   // their ln g / H rows form one span that starts at the row of the first
@@ -270,30 +272,32 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
       hcur = acc ? nh : hcur;
       lcur_lo = acc ? nl : lcur_lo;
     }
-    if (acc) {
-      if (MODEL == kIsing) {
-        lat[widx] = wrow ^ (1u << (x & 31));
+    if (MODEL == kIsing) {
+      // the row word is written back either way (unchanged when rejected)
+      lat[widx] = acc ? wrow ^ (1u << (x & 31)) : wrow;
+    } else if (acc) {
+      if constexpr (NB) {
+        const int sh4 = (site & 7) * 4;
+        lat[widx] = (wrow & ~(15u << sh4)) | ((uint32_t)nv << sh4);
       } else {
-        if constexpr (NB) {
-          const int sh4 = (site & 7) * 4;
-          lat[widx] = (wrow & ~(15u << sh4)) | ((uint32_t)nv << sh4);
-        } else {
-          latb[pbyte(site)] = (unsigned char)nv;
-        }
+        latb[pbyte(site)] = (unsigned char)nv;
       }
-      E += dE;
-      bin = bn;
     }
+    E = acc ? E + dE : E;
+    bin = acc ? bn : bin;
     jcur = acc ? jn : jcur;
-    if (!frozen) {
-      if (PREC == kFP64) {
-        lcur = lcur + lnf;
-        plg[jcur] = lcur;
-      } else {
-        df_add1(hcur, lcur_lo, lnf32, hcur, lcur_lo);
-        plh[jcur] = hcur;
-        pll[jcur] = lcur_lo;
-      }
+    if (PREC == kFP64) {
+      // frozen walkers add 0.0 and count 0: ln g >= +0 always, so x + 0.0
+      // is x bit for bit, and the branch-free form needs no exec mask
+      lcur = lcur + lnf_eff;
+      plg[jcur] = lcur;
+      atomicAdd(&pH[jcur], h_inc);
+    } else if (!frozen) {
+      // a two-float add of 0 could renormalise the pair, so frozen FP32C
+      // walkers skip the update instead
+      df_add1(hcur, lcur_lo, lnf32, hcur, lcur_lo);
+      plh[jcur] = hcur;
+      pll[jcur] = lcur_lo;
       atomicAdd(&pH[jcur], 1u);  // no-return LDS add: the lane owns this word
     }
     // commit the bins fetched one attempt ago, then follow the walker
