@@ -320,37 +320,34 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
       const int up = ((bin + M < hi) ? bin + M : hi) - top;
       const int dn = base - ((bin - M > lo) ? bin - M : lo);
       const int shn = up > 0 ? up : (dn > 0 ? dn : 0);  // 0..D
-      if (shn > 0) {
 #pragma unroll
-        for (int i = 0; i < DMAX; ++i) {
-          if (i < shn) {
-            // up: bin base+i leaves, base+i+PG enters; down: top-i leaves,
-            // top-i-PG enters -- the same slot
-            const int ev = up > 0 ? base + i : top - i;
-            const uint32_t e = eoff + (uint32_t)ev;
-            const uint32_t en = up > 0 ? e + (uint32_t)PG : e - (uint32_t)PG;
-            const int j = prow(ev & PM);
-            if (!frozen) {
-              if (PREC == kFP64) {
-                *at_off(lngw, e << 3) = plg[j];
-              } else {
-                *at_off(lhw, e << 2) = plh[j];
-                *at_off(llw, e << 2) = pll[j];
-              }
-              atomicAdd(at_off(Hw, e << 2), pH[j]);
-            }
-            if (PREC == kFP64) {
-              pend_l[i] = *at_off(lngw, en << 3);
-            } else {
-              pend_hi[i] = *at_off(lhw, en << 2);
-              pend_lo[i] = *at_off(llw, en << 2);
-            }
-            pend_row[i] = j;
+      for (int i = 0; i < DMAX; ++i) {
+        if (i < shn) {
+          // up: bin base+i leaves, base+i+PG enters; down: top-i leaves,
+          // top-i-PG enters -- the same slot.  A frozen walker writes back
+          // its unchanged ln g and no H increments.
+          const int ev = up > 0 ? base + i : top - i;
+          const uint32_t e = eoff + (uint32_t)ev;
+          const uint32_t en = up > 0 ? e + (uint32_t)PG : e - (uint32_t)PG;
+          const int j = prow(ev & PM);
+          if (PREC == kFP64) {
+            *at_off(lngw, e << 3) = plg[j];
+          } else {
+            *at_off(lhw, e << 2) = plh[j];
+            *at_off(llw, e << 2) = pll[j];
           }
+          atomicAdd(at_off(Hw, e << 2), pH[j]);
+          if (PREC == kFP64) {
+            pend_l[i] = *at_off(lngw, en << 3);
+          } else {
+            pend_hi[i] = *at_off(lhw, en << 2);
+            pend_lo[i] = *at_off(llw, en << 2);
+          }
+          pend_row[i] = j;
         }
-        base += up > 0 ? shn : -shn;
-        pend_n = shn;
       }
+      base += up > 0 ? shn : -shn;
+      pend_n = shn;
     }
     ++att;
     return acc;
