@@ -12,8 +12,9 @@ by rewl_autotune before timing (untimed; it restores the state it touched).
 Printed: one JSON line with spin-flip attempts/s, the sweep kernel's
 roofline position (kernel time from HIP events recorded on the library's
 stream), the time to converge of 8 Ising L=8 instances with their error
-against the exact density of states (after the timed region), and the
-single-threaded CPU oracle's attempts/s on a bounded sample.
+against the exact density of states (after the timed region), and the CPU
+oracle's attempts/s on a bounded sample, on one thread and on every host
+core (one independent instance per process).
 
 --workload cfg3 (q=10 Potts L=20, filled with copies) or mix (the batched
 64-instance mix) measures the other forms; --precision fp32c the two-float
@@ -122,6 +123,44 @@ def cpu_baseline(flips, seconds):
             "sample": f"Ising L=32 REWL (16 windows x 8 walkers), {cycles} cycles of {flips} "
                       f"attempts per walker from a fresh start, one thread, {dt:.1f} s",
             "cpu": platform.processor() or platform.machine(), "host_cpus": os.cpu_count()}
+
+
+def _oracle_worker(args):
+    """One process of the all-cores CPU baseline: instance `inst` of cfg2
+    cycled for `seconds`; returns attempts made and the time taken."""
+    inst, flips, seconds = args
+    from oracle import oracle as O
+    from paper_1402_2328_amd import workloads as WL
+    c = WL.CFG2
+    sim = O.Sim(model=c["model"], L=c["L"], n_windows=c["n_windows"],
+                walkers_per_window=c["walkers_per_window"], lnf_final=c["lnf_final"],
+                flips_per_exchange=flips, seed=c["seed"], instance=inst)
+    W = c["n_windows"] * c["walkers_per_window"]
+    cycles = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        sim.sweep(flips)
+        sim.merge()
+        sim.exchange()
+        cycles += 1
+    return cycles * W * flips, time.perf_counter() - t0
+
+
+def cpu_baseline_all_cores(flips, seconds, max_procs=16):
+    """The oracle on every host core at once: independent cfg2 instances, one
+    process each (at most max_procs, the host share of one GPU)."""
+    import multiprocessing as mp
+    n = max(1, min(max_procs, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(n) as pool:
+        res = pool.map(_oracle_worker, [(i, flips, seconds) for i in range(n)])
+    wall = time.perf_counter() - t0
+    att = sum(a for a, _ in res)
+    span = max(t for _, t in res)
+    return {"value": att / span, "unit": "attempts/s", "cores": n, "kind": "oracle",
+            "sample": f"{n} independent Ising L=32 REWL instances (16 windows x 8 walkers), one "
+                      f"process each, {seconds:.0f} s of cycles of {flips} attempts per walker "
+                      f"from a fresh start ({wall:.1f} s wall with start-up)"}
 
 
 def traffic_from_profile(R, flips, page):
@@ -537,6 +576,7 @@ def main():
         out["batching"] = solo_vs_batch(cfgs, a.solo, a.flips, dt / a.steps)
     if not a.no_cpu and a.workload == "cfg2":
         out["cpu_baseline"] = cpu_baseline(a.flips, a.cpu_seconds)
+        out["cpu_baseline_all_cores"] = cpu_baseline_all_cores(a.flips, a.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
