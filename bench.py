@@ -16,13 +16,14 @@ against the exact density of states (after the timed region), and the CPU
 oracle's attempts/s on a bounded sample, on one thread and on every host
 core (one independent instance per process).
 
---workload cfg3 (q=10 Potts L=20, filled with copies) or mix (the batched
+--workload potts10 (q=10 Potts L=20, filled with copies) or mix (the batched
 64-instance mix) measures the other forms; --precision fp32c the two-float
 FP32 ln g.
 
---converge --config {cfg1,cfg2,cfg3,cfg34} [--schedule halving|1t] runs R
+--converge --config {ising8,ising32,potts10,potts10-both} [--schedule
+halving|1t] runs R
 copies of a configuration to ln f <= ln f_final and reports time to
-convergence and the C_V peak (Potts); cfg34 runs the q=10 Potts instances in
+convergence and the C_V peak (Potts); potts10-both runs the q=10 Potts instances in
 FP64 and in two-float FP32 and compares them (progress lines precede the
 JSON line).  --balanced first plans run-time balanced windows (Fig. 1b)
 from a first-iteration pre-run.  --save keeps the normalised ln g and
@@ -71,7 +72,7 @@ def parse():
                          "32 per h for --speedup)")
     ap.add_argument("--flips", type=int, default=10000)
     ap.add_argument("--precision", choices=["fp64", "fp32c"], default="fp64")
-    ap.add_argument("--workload", choices=["cfg2", "cfg3", "mix"], default="cfg2",
+    ap.add_argument("--workload", choices=["ising32", "potts10", "mix"], default="ising32",
                     help="throughput run: Ising L=32 (default), q=10 Potts L=20, or the "
                          "64-instance batched mix")
     ap.add_argument("--page-bins", type=int, default=0,
@@ -83,7 +84,8 @@ def parse():
     ap.add_argument("--no-ttc", action="store_true",
                     help="skip the time-to-converge run (Ising L=8) after the throughput run")
     ap.add_argument("--converge", action="store_true")
-    ap.add_argument("--config", choices=["cfg1", "cfg2", "cfg3", "cfg34"], default="cfg2")
+    ap.add_argument("--config", choices=["ising8", "ising32", "potts10", "potts10-both"],
+                    default="ising32")
     ap.add_argument("--max-minutes", type=float, default=50.0)
     ap.add_argument("--schedule", choices=["halving", "1t"], default="halving")
     ap.add_argument("--speedup", action="store_true")
@@ -106,7 +108,7 @@ def parse():
 def cpu_baseline(flips, seconds):
     from oracle import oracle as O
     from paper_1402_2328_amd import workloads as WL
-    c = WL.CFG2
+    c = WL.ISING_L32
     sim = O.Sim(model=c["model"], L=c["L"], n_windows=c["n_windows"],
                 walkers_per_window=c["walkers_per_window"], lnf_final=c["lnf_final"],
                 flips_per_exchange=flips, seed=c["seed"])
@@ -126,12 +128,12 @@ def cpu_baseline(flips, seconds):
 
 
 def _oracle_worker(args):
-    """One process of the all-cores CPU baseline: instance `inst` of cfg2
-    cycled for `seconds`; returns attempts made and the time taken."""
+    """One process of the all-cores CPU baseline: instance `inst` of the Ising
+    L=32 configuration cycled for `seconds`; returns attempts made and the time taken."""
     inst, flips, seconds = args
     from oracle import oracle as O
     from paper_1402_2328_amd import workloads as WL
-    c = WL.CFG2
+    c = WL.ISING_L32
     sim = O.Sim(model=c["model"], L=c["L"], n_windows=c["n_windows"],
                 walkers_per_window=c["walkers_per_window"], lnf_final=c["lnf_final"],
                 flips_per_exchange=flips, seed=c["seed"], instance=inst)
@@ -147,7 +149,7 @@ def _oracle_worker(args):
 
 
 def cpu_baseline_all_cores(flips, seconds, max_procs=16):
-    """The oracle on every host core at once: independent cfg2 instances, one
+    """The oracle on every host core at once: independent Ising L=32 instances, one
     process each (at most max_procs, the host share of one GPU)."""
     import multiprocessing as mp
     n = max(1, min(max_procs, os.cpu_count() or 1))
@@ -212,17 +214,17 @@ def exact_ising_lng(L):
     return np.array([math.log(v) if v else -np.inf for v in vals])
 
 
-def time_to_converge_cfg1(R=8):
+def time_to_converge_ising8(R=8):
     """Ising L=8 REWL (4 windows x 1 walker, halving to ln f = 1e-6, F=1000)
     run R times to convergence: wall time per instance and its max |ln g
     error| against the exact density of states."""
     from paper_1402_2328_amd import rewl
     from paper_1402_2328_amd import workloads as WL
-    cfg = WL.CFG1
+    cfg = WL.ISING_L8
     F = cfg["flips_per_exchange"]
     ctx = rewl.Context([WL.rewl_params_of(cfg)] * R)
     ctx.autotune(F)
-    done_at, cycles, wall = run_to_convergence(ctx, R, F, 120, "cfg1", quiet=True)
+    done_at, cycles, wall = run_to_convergence(ctx, R, F, 120, "ising8", quiet=True)
     exact = exact_ising_lng(cfg["L"])
     fin = np.isfinite(exact)
     errs = [float(np.max(np.abs(ctx.get_lng(i)[0][fin] - exact[fin]))) for i in sorted(done_at)]
@@ -302,7 +304,7 @@ def balanced_split(cfg, R, alpha, max_s):
 
 def converge(a):
     """Runs R instances of a configuration to ln f <= lnf_final and reports
-    time to convergence, C_V peaks (Potts) and, for --config cfg34, the
+    time to convergence, C_V peaks (Potts) and, for --config potts10-both, the
     two-float FP32 form against FP64 on the same instances.  The normalised
     ln g and jackknife errors of every finished instance are saved to
     --save (an .npz); tests/converge_report.py scores them against exact
@@ -311,8 +313,9 @@ def converge(a):
     from paper_1402_2328_amd import workloads as WL
     name = a.config
     R = a.replicas
-    runs = {"cfg1": [("fp64", WL.CFG1)], "cfg2": [("fp64", WL.CFG2)], "cfg3": [("fp64", WL.CFG3)],
-            "cfg34": [("fp64", WL.CFG3), ("fp32c", WL.CFG4)]}[name]
+    runs = {"ising8": [("fp64", WL.ISING_L8)], "ising32": [("fp64", WL.ISING_L32)],
+            "potts10": [("fp64", WL.POTTS_Q10_L20)],
+            "potts10-both": [("fp64", WL.POTTS_Q10_L20), ("fp32c", WL.POTTS_Q10_L20_FP32C)]}[name]
     sched = WL.ONE_OVER_T if a.schedule == "1t" else WL.HALVING
     out = {"metric": "time to ln f <= ln f_final", "config": name, "schedule": a.schedule,
            "instances": R, "walkers_per_window": a.walkers, "balanced": a.balanced, "runs": {}}
@@ -493,14 +496,14 @@ def main():
         print(json.dumps({"copy_reference_bytes": 4 * x.numel(), "copies": 3, "check": float(y[0])}))
         return
     prec = WL.FP64 if a.precision == "fp64" else WL.FP32C
-    if a.workload == "cfg2":
-        cfg = dict(WL.CFG2, precision=prec, flips_per_exchange=a.flips)
+    if a.workload == "ising32":
+        cfg = dict(WL.ISING_L32, precision=prec, flips_per_exchange=a.flips)
         R = a.replicas or 1024
         cfgs = [cfg] * R
         name = (f"2D Ising L=32 REWL, 16 windows x 8 walkers, 75% overlap, flatness 0.8, "
                 f"F={a.flips} flips per exchange, x{R} independent instances")
-    elif a.workload == "cfg3":
-        cfg = dict(WL.CFG3, precision=prec, flips_per_exchange=a.flips)
+    elif a.workload == "potts10":
+        cfg = dict(WL.POTTS_Q10_L20, precision=prec, flips_per_exchange=a.flips)
         R = a.replicas or WL.bench_replicas(cfg)
         cfgs = [cfg] * R
         name = (f"2D q=10 Potts L=20 REWL, 32 windows x 16 walkers, 75% overlap, flatness 0.8, "
@@ -566,15 +569,15 @@ def main():
         "sweep_attempts_per_s": sweep_rate,
         "stage_of_instance0": int(np.max(st["stage"])),
     }
-    if a.workload != "cfg2" or prec != WL.FP64:
+    if a.workload != "ising32" or prec != WL.FP64:
         # the algorithmic slot count above is that of the FP64 Ising attempt
         out["roofline"] = None
         out["kernel_ms"] = sweep_ms
-    if a.workload == "cfg2" and prec == WL.FP64 and not a.no_ttc:
-        out["time_to_converge"] = time_to_converge_cfg1()
+    if a.workload == "ising32" and prec == WL.FP64 and not a.no_ttc:
+        out["time_to_converge"] = time_to_converge_ising8()
     if a.workload == "mix" and a.solo > 0:
         out["batching"] = solo_vs_batch(cfgs, a.solo, a.flips, dt / a.steps)
-    if not a.no_cpu and a.workload == "cfg2":
+    if not a.no_cpu and a.workload == "ising32":
         out["cpu_baseline"] = cpu_baseline(a.flips, a.cpu_seconds)
         out["cpu_baseline_all_cores"] = cpu_baseline_all_cores(a.flips, a.cpu_seconds)
     print(json.dumps(out), flush=True)

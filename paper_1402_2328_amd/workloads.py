@@ -21,13 +21,13 @@ def config(model, L, q=2, n_windows=1, walkers_per_window=1, lnf_final=1e-8, fli
 
 
 # Ising L=8: 4 windows x 1 walker, ln f 1 -> 1e-6, exchange every 1000 flips
-CFG1 = config(ISING, 8, n_windows=4, walkers_per_window=1, lnf_final=1e-6, flips=1000)
+ISING_L8 = config(ISING, 8, n_windows=4, walkers_per_window=1, lnf_final=1e-6, flips=1000)
 # Ising L=32: 16 windows x 8 walkers, ln f 1 -> 1e-8, exchange every 10^4 flips
-CFG2 = config(ISING, 32, n_windows=16, walkers_per_window=8, lnf_final=1e-8, flips=10000)
+ISING_L32 = config(ISING, 32, n_windows=16, walkers_per_window=8, lnf_final=1e-8, flips=10000)
 # Potts q=10 L=20: 32 windows x 16 walkers
-CFG3 = config(POTTS, 20, q=10, n_windows=32, walkers_per_window=16, lnf_final=1e-8, flips=10000)
+POTTS_Q10_L20 = config(POTTS, 20, q=10, n_windows=32, walkers_per_window=16, lnf_final=1e-8, flips=10000)
 # the same with two-float FP32 ln g
-CFG4 = dict(CFG3, precision=FP32C)
+POTTS_Q10_L20_FP32C = dict(POTTS_Q10_L20, precision=FP32C)
 
 
 def bench_replicas(cfg, n_cu=256):

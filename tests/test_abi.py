@@ -39,27 +39,27 @@ def test_strerror_names_codes():
                                  dict(overlap=(4, 4)), dict(n_windows=400), dict(schedule=2),
                                  dict(schedule=-1), dict(q=128, model=workloads.POTTS)])
 def test_workspace_bytes_rejects_bad_parameters(bad):
-    cfg = dict(workloads.CFG1)
+    cfg = dict(workloads.ISING_L8)
     cfg.update(bad)
     assert rewl.rewl_workspace_bytes([workloads.rewl_params_of(cfg)]) == 0
 
 
 def test_workspace_bytes_for_configs():
-    for cfg in (workloads.CFG1, workloads.CFG2, workloads.CFG3, workloads.CFG4):
+    for cfg in (workloads.ISING_L8, workloads.ISING_L32, workloads.POTTS_Q10_L20, workloads.POTTS_Q10_L20_FP32C):
         n = rewl.rewl_workspace_bytes([workloads.rewl_params_of(cfg)])
         assert 0 < n < 64 * 2 ** 20
-    p = [workloads.rewl_params_of(workloads.CFG2)]
+    p = [workloads.rewl_params_of(workloads.ISING_L32)]
     assert rewl.rewl_workspace_bytes(p * 4) > 2 * rewl.rewl_workspace_bytes(p)
 
 
 def test_mixed_precision_batch_rejected():
-    a = dict(workloads.CFG1)
-    b = dict(workloads.CFG1, precision=workloads.FP32C)
+    a = dict(workloads.ISING_L8)
+    b = dict(workloads.ISING_L8, precision=workloads.FP32C)
     assert rewl.rewl_workspace_bytes([workloads.rewl_params_of(a), workloads.rewl_params_of(b)]) == 0
 
 
 def test_explicit_windows_validated():
-    p = [workloads.rewl_params_of(workloads.CFG1)]
+    p = [workloads.rewl_params_of(workloads.ISING_L8)]
     good = [([0, 9, 18, 27], [37, 46, 55, 64])]
     assert rewl.rewl_workspace_bytes(p, good) > 0
     for bad in ([([0, 9, 18, 27], [37, 46, 55, 65])],        # beyond the range
@@ -69,12 +69,12 @@ def test_explicit_windows_validated():
 
 
 def test_reserved_parameter_field_must_be_zero():
-    p = workloads.rewl_params_of(workloads.CFG1)
+    p = workloads.rewl_params_of(workloads.ISING_L8)
     assert rewl.rewl_workspace_bytes([p]) > 0
     p.reserved = 1
     assert rewl.rewl_workspace_bytes([p]) == 0
 
 
 def test_one_over_t_configs_lay_out():
-    cfg = dict(workloads.CFG2, schedule=workloads.ONE_OVER_T, walkers_per_window=64)
+    cfg = dict(workloads.ISING_L32, schedule=workloads.ONE_OVER_T, walkers_per_window=64)
     assert rewl.rewl_workspace_bytes([workloads.rewl_params_of(cfg)]) > 0

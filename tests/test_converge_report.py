@@ -14,7 +14,7 @@ def test_exact_input_scores_zero_and_offsets_are_seen(tmp_path):
     k = np.nonzero(fin)[0][5]
     bumped[k] += 0.03
     f = tmp_path / "run.npz"
-    np.savez(f, config="cfg1", model=0, L=8, q=2,
+    np.savez(f, config="ising8", model=0, L=8, q=2,
              fp64_instances=np.array([0, 1]), fp64_lng=np.array([exact, bumped]),
              fp64_jk_err=np.array([np.zeros_like(exact), np.zeros_like(exact)]))
     r = converge_report.report(str(f))["runs"]["fp64"]

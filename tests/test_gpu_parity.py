@@ -253,9 +253,9 @@ def test_page_size_and_group_shape_do_not_change_results(name, page, group, prod
         compare_state(ctx, 0, sim)
 
 
-@pytest.mark.parametrize("cfg_name,replicas,sample", [("CFG2", 0, (0, 1, -1)),
-                                                      ("CFG3", 3, (0, 2)),
-                                                      ("CFG4", 2, (1,))])
+@pytest.mark.parametrize("cfg_name,replicas,sample", [("ISING_L32", 0, (0, 1, -1)),
+                                                      ("POTTS_Q10_L20", 3, (0, 2)),
+                                                      ("POTTS_Q10_L20_FP32C", 2, (1,))])
 def test_full_size_configs_sampled(cfg_name, replicas, sample):
     """Full-size workloads in the launch shape the benchmark uses; sampled
     instances are checked walker by walker against the oracle."""
@@ -328,11 +328,11 @@ def test_balanced_split_pipeline_matches_oracle():
     lo, hi = rewl.balanced_windows(g["nbins"], h, g["lo"], g["hi"], mean)
     olo, ohi = oracle_balanced(g["nbins"], h, (3, 4), list(g["lo"]), list(g["hi"]), list(mean))
     assert list(lo) == olo and list(hi) == ohi
-    cfg2 = [dict(c, seed=c["seed"] + 4) for c in cfgs]
-    windows = [(lo, hi)] * len(cfg2)
-    ctx2 = gpu_context(cfg2, windows=windows)
+    later = [dict(c, seed=c["seed"] + 4) for c in cfgs]
+    windows = [(lo, hi)] * len(later)
+    ctx2 = gpu_context(later, windows=windows)
     ctx2.run_to_convergence(F, cycles_per_check=100)
-    for i, c in enumerate(cfg2):
+    for i, c in enumerate(later):
         sim = oracle_sim(c, instance=i, windows=(lo, hi))
         sim.run(10 ** 6)
         compare_state(ctx2, i, sim)

@@ -171,8 +171,8 @@ def test_rewl_ising_L4_matches_brute_force():
     assert max(errs) < 0.13, errs
 
 
-def test_cfg1_ising_L8_matches_exact():
-    """cfg1: L=8, 4 windows, 1 walker, F=1000, ln f 1 -> 1e-6."""
+def test_ising_L8_h4_m1_matches_exact():
+    """Ising L=8, 4 windows, 1 walker, F=1000, ln f 1 -> 1e-6."""
     exact = X.ln_g(load_ising_table(8))
     errs = []
     for seed in range(1, 9):
