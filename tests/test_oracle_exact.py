@@ -1,4 +1,4 @@
-"""Pins for the exact densities of states used to judge the oracle (CPU).
+"""Pins for the exact densities of states the oracle is checked against (CPU).
 
 Brute force, a transfer matrix, Kaufman's torus formula and Onsager's bulk
 free energy are independent routes; they are checked against each other and
