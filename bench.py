@@ -383,8 +383,9 @@ def speedup(a):
     Sec. 4): N is the number of MC steps per walker the slowest window needs
     to finish its first WL iteration.  Ising L x L (default 32), or
     q-state Potts with --q, m walkers per window, overlap 75 %, exchange
-    every F flips.  Every h runs as R
-    independent instances in one batched context; N(h) is their median.
+    every F flips.  Every h runs as R independent instances in one batched
+    context; N(h) is their median.  N_single is one walker on the whole
+    range (with m > 1 it gets a run of its own).
     Then the run-time balanced split (Fig. 1b) is planned per h from the
     equal-split runs (rewl_balanced_windows on the mean per-window first
     iteration steps) and measured on R other seeds; a third pass re-plans
@@ -398,11 +399,11 @@ def speedup(a):
     base = WL.config(model, a.L, q=a.q, n_windows=1, walkers_per_window=m, lnf_final=0.5, flips=F)
     what = f"2D q={a.q} Potts L={a.L}" if model == WL.POTTS else f"2D Ising L={a.L}"
 
-    def measure(tag, split, seed0):
+    def measure(tag, split, seed0, mm=m):
         cfgs, windows = [], []
         for h in split:
             for r in range(R):
-                cfgs.append(dict(base, n_windows=h, seed=seed0 + r))
+                cfgs.append(dict(base, n_windows=h, walkers_per_window=mm, seed=seed0 + r))
                 windows.append(split[h])
         explicit = windows[0] is not None
         assert all((w is not None) == explicit for w in windows)
@@ -430,7 +431,12 @@ def speedup(a):
         return res, time.perf_counter() - t0
 
     eq, t_eq = measure("equal", {h: None for h in hs}, 1)
-    N1 = eq[hs[0]]["N_median"] if hs[0] == 1 else None
+    if m == 1:
+        N1 = eq[hs[0]]["N_median"] if hs[0] == 1 else None
+    else:
+        # N_single is one walker on the whole range (h = m = 1)
+        single, _ = measure("single walker", {1: None}, 1 + 3 * R, mm=1)
+        N1 = single[1]["N_median"]
 
     def plan(runs, h):
         lo = np.concatenate([r[h]["lo"] for r in runs])
@@ -449,7 +455,7 @@ def speedup(a):
             out[str(h)] = {"N_slowest_median": r["N_median"], "speedup": s_, "finished": r["finished"],
                            "windows_lo": [int(x) for x in r["lo"]]}
         pts = [(h, v["speedup"]) for h, v in ((int(k), v) for k, v in out.items()) if v["speedup"]]
-        if N1:
+        if N1 and m == 1:
             pts = [(1, 1.0)] + [p for p in pts if p[0] != 1]
         slope = None
         if len(pts) >= 2:
