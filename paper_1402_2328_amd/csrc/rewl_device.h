@@ -162,24 +162,35 @@ __device__ __forceinline__ bool accept32_flat(uint32_t u, float delta) {
   return (float)u < ldexpf(p, n + 24);
 }
 
+// Median of three signed integers (v_med3_i32): clamp(a, b, c) when b <= c.
+__device__ __forceinline__ int med3_i32(int a, int b, int c) {
+  int r;
+  asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+
 // Fast exact acceptance.  A single-precision estimate e of exp(x), x the
 // clamped delta, from the hardware base-2 exponential of x log2(e) has a
 // relative error below 1e-5: x and log2(e) rounded to float (each < 2^-24
 // relative, |x| <= 40) and the product rounded (< 58 * 2^-24 absolute) shift
 // the exponent by < 1e-5 in total, and the instruction itself is accurate to
-// about one float ulp.  With the slack s = 2^-10, far above that bound, the
-// uniform u = u53 * 2^-53, which lies in [hi 2^-32, (hi + 1) 2^-32), is
-// surely below exp_det(x) when (hi + 1) 2^-32 <= e (1 - s) and surely not
-// when hi 2^-32 >= e (1 + s); only in between (probability about 2 s e per
+// about one float ulp.  The uniform u = u53 * 2^-53 lies in
+// [hi 2^-32, (hi + 1) 2^-32).  With the slack s = 2^-10, far above that
+// bound and above the float roundings of hi, hi + 1 and the two products
+// (each < 2^-24 relative), u is surely below exp_det(x) when
+// fl(fl(hi) + 1) <= fl(e (1 - s) 2^32), and surely not when
+// fl(hi) > fl(e (1 + s) 2^32); only in between (probability about 2 s e per
 // attempt) is accept64_flat evaluated.  The decision is therefore always
-// accept64_flat's.  Comparisons are in FP64 on exact conversions, with the
-// power of two moved onto e.
+// accept64_flat's.  The estimate uses the unclamped delta: for delta >= 0
+// only the first test can hold (e >= 1), and it is right since every such
+// move is accepted; for delta < -40 the second test holds exactly when
+// hi >= 1, and then u >= 2^-32 > exp_det(-40), a rejection; hi = 0 goes to
+// the exact test.
 __device__ __forceinline__ bool accept64_fast(uint32_t hi, uint32_t lo, double delta) {
-  const double x = fmin(fmax(delta, -40.0), 0.0);
-  const double e = (double)__builtin_amdgcn_exp2f((float)x * 0x1.715476p+0f);
-  const double h = (double)hi;
-  const bool yes = h + 1.0 <= e * ((1.0 - 0x1p-10) * 0x1p32);
-  const bool no = h >= e * ((1.0 + 0x1p-10) * 0x1p32);
+  const float e = __builtin_amdgcn_exp2f((float)delta * 0x1.715476p+0f);
+  const float h = (float)hi;
+  const bool yes = h + 1.0f <= e * 0x1.ff8p+31f;  // (1 - 2^-10) 2^32
+  const bool no = h > e * 0x1.004p+32f;           // (1 + 2^-10) 2^32
   bool a = yes;
   if (!yes && !no) a = accept64_flat(hi, lo, delta);
   return a;

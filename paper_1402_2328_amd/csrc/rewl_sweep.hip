@@ -142,15 +142,14 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
   float* const llw = PREC == kFP64 ? nullptr : P.llo + gb0;
   uint32_t* const Hw = P.H + gb0;
 
-  int32_t E = P.E[g];
+  // the energy is tracked as its bin: E = emin + bin * binw
   uint64_t att = P.att[g];
-  int bin = (E - Ig.emin) >> bshift;
+  int bin = (P.E[g] - Ig.emin) >> bshift;
   if (bin < lo || bin > hi) {
     // only reachable through corrupted state: flag the instance and keep
     // every access inside the window (the instance's results are void)
     atomicMin(&P.ist[wg.inst].error, -6);
     bin = bin < lo ? lo : hi;
-    E = Ig.emin + (bin << bshift);
   }
 
   // ---- stage in the lattice ----
@@ -187,6 +186,8 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
     base = base > hi - PM ? hi - PM : base;
   }
   const int cnt = paged ? PG : nb;
+  const int hi_pm = hi - PM;  // highest page start
+  const int m_pm = M - PM;
   for (int i = 0; i < cnt; ++i) {
     const int b = base + i;
     const int j = __mul24(b & PM, S) + lane;
@@ -232,12 +233,14 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
   // bin, acceptance, lattice and ln g / H update, page follow.  Without a
   // producer, the last two Philox slices of the block in flight (rn) are
   // placed beside the ln g read and the exponential.
-  auto complete = [&](const uint4 r, uint4& rn, int dE, int db, int nv, int widx, uint32_t wrow,
-                      int x, int site, auto nbt) -> bool {
+  // bn is the proposed bin.  bn & PM always names a slot of the page, so the
+  // ln g read stays in bounds when bn lies outside the window; its value is
+  // then not used.
+  auto complete = [&](const uint4 r, uint4& rn, int bn, int nv, uint32_t wofs, uint32_t wrow,
+                      uint32_t fm, int site, auto nbt) -> bool {
     constexpr bool NB = decltype(nbt)::value;
-    const int bn = bin + db;
     const bool inwin = (bn >= lo) && (bn <= hi);
-    const int jn = inwin ? prow(bn & PM) : jcur;
+    const int jn = prow(bn & PM);
     bool acc;
     if (PREC == kFP64) {
       const double ln = plg[jn];
@@ -274,16 +277,15 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
     }
     if (MODEL == kIsing) {
       // the row word is written back either way (unchanged when rejected)
-      lat[widx] = acc ? wrow ^ (1u << (x & 31)) : wrow;
+      *reinterpret_cast<uint32_t*>(lds + wofs) = acc ? wrow ^ fm : wrow;
     } else if (acc) {
       if constexpr (NB) {
         const int sh4 = (site & 7) * 4;
-        lat[widx] = (wrow & ~(15u << sh4)) | ((uint32_t)nv << sh4);
+        *reinterpret_cast<uint32_t*>(lds + wofs) = (wrow & ~(15u << sh4)) | ((uint32_t)nv << sh4);
       } else {
         latb[pbyte(site)] = (unsigned char)nv;
       }
     }
-    E = acc ? E + dE : E;
     bin = acc ? bn : bin;
     jcur = acc ? jn : jcur;
     if (PREC == kFP64) {
@@ -316,19 +318,23 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
     }
     pend_n = 0;
     if (paged) {
+      // bin + M - PM is the lowest page start that still covers bin + M,
+      // bin - M the highest that covers bin - M (PM >= 2M); the start then
+      // stays inside [lo, hi - PM].  Both are integer medians.
       const int top = base + PM;
-      const int up = ((bin + M < hi) ? bin + M : hi) - top;
-      const int dn = base - ((bin - M > lo) ? bin - M : lo);
-      const int shn = up > 0 ? up : (dn > 0 ? dn : 0);  // 0..D
+      const int nbase = med3_i32(med3_i32(base, bin + m_pm, bin - M), lo, hi_pm);
+      const int sft = nbase - base;  // -D..D
+      const bool up = sft > 0;
+      const int shn = up ? sft : -sft;
 #pragma unroll
       for (int i = 0; i < DMAX; ++i) {
         if (i < shn) {
           // up: bin base+i leaves, base+i+PG enters; down: top-i leaves,
           // top-i-PG enters -- the same slot.  A frozen walker writes back
           // its unchanged ln g and no H increments.
-          const int ev = up > 0 ? base + i : top - i;
+          const int ev = up ? base + i : top - i;
           const uint32_t e = eoff + (uint32_t)ev;
-          const uint32_t en = up > 0 ? e + (uint32_t)PG : e - (uint32_t)PG;
+          const uint32_t en = up ? e + (uint32_t)PG : e - (uint32_t)PG;
           const int j = prow(ev & PM);
           if (PREC == kFP64) {
             *at_off(lngw, e << 3) = plg[j];
@@ -346,7 +352,7 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
           pend_row[i] = j;
         }
       }
-      base += up > 0 ? shn : -shn;
+      base = nbase;
       pend_n = shn;
     }
     ++att;
@@ -359,15 +365,48 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
   // ln g read is issued, and beside the exponential.  sched_barrier keeps
   // the compiler from hoisting the slices back together.
   // One attempt with Philox block r; without a producer it also computes
-  // rn, the block of the next attempt, in slices.  P2 (L a power of two) and
-  // NB (Potts nibbles) are compile-time copies of the loop, chosen once per
-  // launch, so that no branch splits the attempt's scheduling region.
-  auto attempt = [&](const uint4 r, uint4& rn, auto p2t, auto nbt) {
-    constexpr bool P2 = decltype(p2t)::value;
+  // rn, the block of the next attempt, in slices.  The lattice form LK
+  // (0: any L, 1: L a power of two, 2: Ising with L = 32, one word per row)
+  // and NB (Potts nibbles) select compile-time copies of the loop, chosen
+  // once per launch, so that no branch splits the attempt's scheduling
+  // region.
+  auto attempt = [&](const uint4 r, uint4& rn, auto lkt, auto nbt) {
+    constexpr int LK = decltype(lkt)::value;
+    constexpr bool P2 = LK >= 1;
     constexpr bool NB = decltype(nbt)::value;
     const uint64_t an = att + 1;
     const uint4 cn = make_uint4((uint32_t)an, (uint32_t)(an >> 32), (uint32_t)loc, tagw);
     const int site = (int)__umulhi(r.x, (uint32_t)N);
+    if constexpr (LK == 2) {
+      // Ising, L = 32: row y = site / 32 is one word, column x = site % 32.
+      // Rotating the row right by x puts the spin at bit 0 and its right
+      // neighbour at bit 1; one more rotation left puts the left neighbour
+      // at bit 0 and the spin at bit 1.  Word shifts and rotations use the
+      // low five bits of site, which is x.  The bin step is
+      // db = (agreeing neighbours) - 2 (Delta E = 2 s sum, in bins of 4).
+      const int y = site >> 5;
+      const uint32_t aw = __mul24((uint32_t)y, (uint32_t)S4) + (uint32_t)lane4;
+      const uint32_t ad = __mul24((uint32_t)((y + 1) & 31), (uint32_t)S4) + (uint32_t)lane4;
+      const uint32_t au = __mul24((uint32_t)((y - 1) & 31), (uint32_t)S4) + (uint32_t)lane4;
+      const uint32_t wrow = *reinterpret_cast<const uint32_t*>(lds + aw);
+      const uint32_t wd = *reinterpret_cast<const uint32_t*>(lds + ad);
+      const uint32_t wu = *reinterpret_cast<const uint32_t*>(lds + au);
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (!PROD) {
+        rn = philox_rounds<0, 4>(cn, k0, k1);
+        REWL_PIN4(rn);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      const uint32_t fm = 1u << (site & 31);
+      const uint32_t tr = __builtin_amdgcn_alignbit(wrow, wrow, (uint32_t)site);
+      const uint32_t tl = __builtin_amdgcn_alignbit(tr, tr, 31u);
+      const uint32_t hz = ~(tl ^ tr) & 3u;     // left and right agree with the spin
+      const uint32_t vd = ~(wd ^ wrow) & fm;   // lower neighbour agrees
+      const uint32_t vu = ~(wu ^ wrow) & fm;   // upper neighbour agrees
+      const int bn = bin - 2 + __builtin_popcount(hz) + __builtin_popcount(vd) + __builtin_popcount(vu);
+      complete(r, rn, bn, 0, aw, wrow, fm, site, nbt);
+      return;
+    }
     int y, x, xr, xl, yd, yu;
     if constexpr (P2) {  // shifts and masks
       y = site >> lgL;
@@ -384,9 +423,9 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
       yd = (y + 1 == L) ? 0 : y + 1;
       yu = (y == 0) ? L - 1 : y - 1;
     }
-    int dE, db, nv = 0;
+    int db, nv = 0;
     int widx = 0;
-    uint32_t wrow = 0;
+    uint32_t wrow = 0, fm = 0;
     if (MODEL == kIsing) {
       // bit b of a row word: spin at x = 32 * part + b is +1
       int s0, a, b, c, d;
@@ -428,7 +467,7 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
       }
       // sigma = 2 bit - 1: dE = 2 s0 (sum of neighbours), bin step dE / 4
       db = (2 * s0 - 1) * (a + b + c + d - 2);
-      dE = 4 * db;
+      fm = 1u << (x & 31);
     } else {
       const int rowy = __mul24(y, L);
       int s0, a, b, c, d;
@@ -457,24 +496,23 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
       int v = s0 + 1 + (int)__umulhi(r.y, (uint32_t)(q - 1));
       v = (v >= q) ? v - q : v;
       nv = v;
-      dE = ((a == s0) + (b == s0) + (c == s0) + (d == s0)) -
-           ((a == v) + (b == v) + (c == v) + (d == v));
+      const int dE = ((a == s0) + (b == s0) + (c == s0) + (d == s0)) -
+                     ((a == v) + (b == v) + (c == v) + (d == v));
       db = dE >> bshift;
     }
-    complete(r, rn, dE, db, nv, widx, wrow, x, site, nbt);
-    (void)cn;
+    complete(r, rn, bin + db, nv, 4u * (uint32_t)widx, wrow, fm, site, nbt);
   };
 
 
   using T = std::true_type;
   using F = std::false_type;
 
-  auto run = [&](auto p2t, auto nbt) {
+  auto run = [&](auto lkt, auto nbt) {
     if constexpr (!PROD) {
       uint4 r = philox10(make_uint4((uint32_t)att, (uint32_t)(att >> 32), (uint32_t)loc, tagw), k0, k1);
       for (int64_t t = 0; t < flips; ++t) {
         uint4 rn;
-        attempt(r, rn, p2t, nbt);
+        attempt(r, rn, lkt, nbt);
         r = rn;
       }
     } else {
@@ -486,19 +524,24 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
         for (int i = 0; i < n; ++i) {
           const uint4 rnext = src[(size_t)(i + 1 < n ? i + 1 : i) * S];
           uint4 unused;
-          attempt(r, unused, p2t, nbt);
+          attempt(r, unused, lkt, nbt);
           r = rnext;
         }
         __syncthreads();  // chunk c consumed, chunk c + 1 written
       }
     }
   };
+  using L0 = std::integral_constant<int, 0>;
+  using L1 = std::integral_constant<int, 1>;
+  using L2 = std::integral_constant<int, 2>;
   if (MODEL == kPotts && nib) {
-    if (pow2) run(T{}, T{});
-    else run(F{}, T{});
+    if (pow2) run(L1{}, T{});
+    else run(L0{}, T{});
+  } else if (MODEL == kIsing && ROWW == 1 && L == 32) {
+    if constexpr (MODEL == kIsing && ROWW == 1) run(L2{}, F{});
   } else {
-    if (pow2) run(T{}, F{});
-    else run(F{}, F{});
+    if (pow2) run(L1{}, F{});
+    else run(L0{}, F{});
   }
 
   // ---- stage out ----
@@ -549,7 +592,7 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
     const int nwi = (N + 3) >> 2;
     for (int i = 0; i < nwi; ++i) dst[i] = lat[i * S + lane];
   }
-  P.E[g] = E;
+  P.E[g] = Ig.emin + (bin << bshift);  // every energy sits on the bin grid
   P.att[g] = att;
 }
 
