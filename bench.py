@@ -7,7 +7,8 @@ merge) and rewl_exchange (one replica-exchange round).  The workload is the
 flatness 0.8, exchange every 10^4 flips, FP64 ln g) replicated R times as
 independent instances so that the chip is filled; each copy carries its
 instance index in every random-number counter.  The launch shape is chosen
-by rewl_autotune before timing (untimed; it restores the state it touched).
+by rewl_autotune after the warm-up steps, on the state the timed steps start
+from (untimed; it restores the state it touched).
 
 Printed: one JSON line with spin-flip attempts/s, the sweep kernel's
 roofline position (kernel time from HIP events recorded on the library's
@@ -50,10 +51,11 @@ CLOCK_HZ = 2.4e9
 VALU_LANE_OPS_PER_CLK_PER_CU = 64          # 4 SIMD x 16 lanes, full-rate 32-bit / FP64 ops
 PEAK_VALU = N_CU * VALU_LANE_OPS_PER_CLK_PER_CU * CLOCK_HZ   # 3.93e13 lane-op/s
 # Algorithmic VALU work of one attempt in full-rate lane-op slots:
-# Philox4x32-10 120 (20 32x32->64 multiplies at 4 slots + 40 xors), site and
-# neighbour indexing 24, energy change and window test 8, acceptance with
-# the exponential 26, update 8.
-VALU_SLOTS_PER_ATTEMPT = 186
+# Philox4x32-10 60 (20 32x32->64 multiplies, one slot each since the wide
+# multiply issues at the full rate on gfx950, see --alu-rate, and 40
+# two-input xors), site and neighbour indexing 24, energy change and window
+# test 8, acceptance with the exponential 26, update 8.
+VALU_SLOTS_PER_ATTEMPT = 126
 # Algorithmic LDS bytes of one attempt (Ising L=32): three 4-byte lattice rows
 # read, 8 B ln g read, 8 B ln g written, 4 B histogram read-modify-write
 # (counted 8), 4 B lattice row written on acceptance (~0.5).
@@ -102,6 +104,8 @@ def parse():
                     help="--converge on the run-time balanced split planned from a pre-run")
     ap.add_argument("--copy-reference", action="store_true",
                     help="only copy a 512 MiB device buffer 3 times (HBM counter calibration)")
+    ap.add_argument("--alu-rate", action="store_true",
+                    help="only measure the issue cost of the VALU forms the sweep uses")
     return ap.parse_args()
 
 
@@ -474,6 +478,30 @@ def speedup(a):
     return out
 
 
+def alu_rate(iters=4096):
+    """Issue cost of the instruction forms of the sweep, in full-rate slots
+    (ns per wavefront step per SIMD, divided by that of a one-slot op)."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_1402_2328_amd", "libalurate.so")
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: run __graft_entry__.build() first")
+    lib = ctypes.CDLL(path)
+    lib.alu_rate.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_int32]
+    lib.alu_rate.restype = ctypes.c_int
+    out = (ctypes.c_double * 5)()
+    rc = lib.alu_rate(iters, out, 5)
+    if rc != 0:
+        raise RuntimeError(f"alu_rate failed ({rc})")
+    ns = list(out)
+    forms = ["v_xad_u32", "v_mad_u64_u32 + v_xor_b32", "v_mul_lo_u32 + v_mul_hi_u32 + v_xor_b32",
+             "v_fma_f64", "v_bitop3_b32"]
+    one = ns[0]
+    return {"metric": "VALU issue cost per wavefront step, 8 waves per SIMD",
+            "ns_per_wave_step": dict(zip(forms, ns)),
+            "slots": dict(zip(forms, [v / one for v in ns])),
+            "clock_ghz_if_one_slot_is_4_cycles": 4.0 / one}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -492,6 +520,9 @@ def main():
         return
     if a.speedup:
         print(json.dumps(speedup(a)), flush=True)
+        return
+    if a.alu_rate:
+        print(json.dumps(alu_rate()), flush=True)
         return
     if a.copy_reference:
         x = torch.empty(128 * 2 ** 20, dtype=torch.float32, device="cuda")
@@ -520,7 +551,8 @@ def main():
         name = (f"batched mix of 64 Ising/Potts REWL instances (L 16-64, q 2-10, 8-48 windows x "
                 f"4-16 walkers), F={a.flips} flips per exchange, x{R}")
     ctx = rewl.Context([WL.rewl_params_of(c) for c in cfgs])
-    plan = ctx.set_launch(page_bins=a.page_bins) if a.page_bins > 0 else ctx.autotune(a.flips)
+    if a.page_bins > 0:
+        plan = ctx.set_launch(page_bins=a.page_bins)
     W = sum(c["n_windows"] * c["walkers_per_window"] for c in cfgs)
     stream = ctx.stream
 
@@ -535,6 +567,9 @@ def main():
 
     for _ in range(a.warmup):
         step()
+    if a.page_bins <= 0:
+        # tuned on the state the timed steps start from (tuning restores it)
+        plan = ctx.autotune(a.flips, repeats=3)
     torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(a.steps)]

@@ -147,15 +147,18 @@ int rewl_run_sweeps(rewl_ctx* ctx, int64_t flips);
 int rewl_set_launch(rewl_ctx* ctx, int32_t cls, int32_t page_bins, int32_t walkers_per_group,
                     int32_t rng_producer, int32_t potts_nibbles, int32_t* out);
 
-/* Measures `repeats` sweeps of `flips` attempts for each candidate shape
- * (every allowed power-of-two page, with and without the RNG producer, Potts
- * spins as nibbles or bytes) of
- * every class, class by class with the other classes at their best shape so
- * far, and keeps the fastest.  Sweeps
- * of different classes run concurrently, so every candidate is timed on
- * the whole batch.
+/* Chooses the launch shape of every class by timing sweeps of `flips`
+ * attempts (mean of `repeats` sweeps per candidate) on the whole batch:
+ * classes sweep side by side and share the compute units, so a candidate
+ * replaces the best plan only when the batch is faster with it.  Candidates
+ * are first one page size for all classes (with and without the RNG
+ * producer, Potts spins as nibbles or bytes), then, in two passes over the
+ * classes, every shape of one class with the others at their best so far.
+ * The plan in force before the call is the first candidate, so tuning never
+ * keeps a slower plan than it started from.
  * The simulation state is saved to host memory first and restored
- * afterwards, so tuning changes nothing but the launch shape.  out: as for rewl_set_launch.  Synchronises.
+ * afterwards, so tuning changes nothing but the launch shape.  out: as for
+ * rewl_set_launch.  Synchronises.
  * Errors: INVAL, HIP. */
 int rewl_autotune(rewl_ctx* ctx, int64_t flips, int32_t repeats, int32_t* out);
 

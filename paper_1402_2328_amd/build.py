@@ -17,6 +17,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librewl.so")
+ALU_LIB = os.path.join(HERE, "libalurate.so")
 SOURCES = ["rewl_sweep.hip", "rewl_kernels.hip", "rewl_api.cpp", "rewl_plan.cpp"]
 ARCH = os.environ.get("REWL_OFFLOAD_ARCH", "gfx950")
 
@@ -46,7 +47,19 @@ def build(verbose=False):
     tmp = LIB + ".tmp"
     subprocess.check_call([hipcc(), "-shared", f"--offload-arch={ARCH}", *objs, "-o", tmp])
     os.replace(tmp, LIB)
+    build_alu_rate(verbose)
     return LIB
+
+
+def build_alu_rate(verbose=False):
+    """libalurate.so: the instruction issue-cost probe behind the sweep's roofline."""
+    tmp = ALU_LIB + ".tmp"
+    cmd = [hipcc(), *flags(), "-shared", "-x", "hip", os.path.join(CSRC, "alu_rate.hip"), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, ALU_LIB)
+    return ALU_LIB
 
 
 if __name__ == "__main__":

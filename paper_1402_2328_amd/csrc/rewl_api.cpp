@@ -410,12 +410,10 @@ int d2h(rewl_ctx* c, T* dst, const void* src, size_t count) {
   return sync(c);
 }
 
-hipError_t enqueue_sweeps(rewl_ctx* c, int64_t flips, int only_class = -1) {
+hipError_t enqueue_sweeps(rewl_ctx* c, int64_t flips) {
   int active[3], n = 0;
-  for (int cls = 0; cls < 3; ++cls) {
-    if (only_class >= 0 && cls != only_class) continue;
+  for (int cls = 0; cls < 3; ++cls)
     if (c->plan.cls[cls].count > 0) active[n++] = cls;
-  }
   const bool fork = n > 1 && c->side[0] != nullptr;
   hipError_t e = hipSuccess;
   if (fork) {
@@ -634,45 +632,83 @@ int rewl_autotune(rewl_ctx* c, int64_t flips, int32_t repeats, int32_t* out) {
   if (rc) return rc;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return REWL_E_HIP;
+  // Every timing starts from the snapshot: the same walkers do the same
+  // attempts for every candidate.
+  // The time of a plan is the mean of `repeats` sweeps (the placement of
+  // concurrent classes on the compute units varies from sweep to sweep).
+  auto time_plan = [&](const LaunchPlan& pl, float& ms) -> int {
+    LaunchPlan q = pl;
+    fill_table(L, q);
+    int r = install_plan(c, q);
+    ms = 0.0f;
+    for (int k = 0; k < repeats && !r; ++k) {
+      r = hip_rc(hipMemcpyAsync(c->ws, snap.data(), c->lo.o_wg, hipMemcpyHostToDevice, c->stream));
+      if (!r) r = hip_rc(hipMemcpyAsync(c->ws + L.o_ist, snap.data() + L.o_ist, L.total - L.o_ist,
+                                         hipMemcpyHostToDevice, c->stream));
+      if (!r) r = hip_rc(hipEventRecord(e0, c->stream));
+      if (!r) r = hip_rc(enqueue_sweeps(c, flips));
+      if (!r) r = hip_rc(hipEventRecord(e1, c->stream));
+      if (!r) r = sync(c);
+      float t = 0.0f;
+      if (!r) r = hip_rc(hipEventElapsedTime(&t, e0, e1));
+      ms += t / (float)repeats;
+    }
+    return r;
+  };
+  // Classes sweep side by side and share the compute units, so every
+  // candidate is timed on the whole batch, and a candidate replaces the
+  // best plan only when the whole batch is faster with it.
   LaunchPlan best = c->plan;
-  for (int cls = 0; cls < 3 && !rc; ++cls) {
+  float best_ms = 0.0f;
+  rc = time_plan(best, best_ms);
+  auto consider = [&](const LaunchPlan& pl) -> int {
+    float ms = 0.0f;
+    const int r = time_plan(pl, ms);
+    if (!r && ms < best_ms) {
+      best_ms = ms;
+      best = pl;
+    }
+    return r;
+  };
+  // Seeds: one page for every class (clamped to each class's useful
+  // range), with and without the RNG producer, Potts spins as nibbles or
+  // bytes.
+  int pmin_all = 1 << 30, pmax_all = 0;
+  for (int cls = 0; cls < 3; ++cls) {
     if (L.walkers[cls] == 0) continue;
-    std::vector<int> cands;
     int pmin, pmax;
     page_range(L, cls, pmin, pmax);
-    for (int p = pmin; p <= pmax; p <<= 1) cands.push_back(p);
-    float best_ms = -1.0f;
-    struct Shape {
-      int page, prod, nib;
-    };
-    std::vector<Shape> shapes;
-    for (int p : cands)
-      for (int prod = 0; prod < 2; ++prod)
-        for (int nib = 0; nib < (cls == 2 && L.nib_ok[cls] ? 2 : 1); ++nib) shapes.push_back({p, prod, nib});
-    for (const Shape& shp : shapes) {
-      LaunchPlan pl = best;
-      if (plan_class(L, cls, budget, shp.page, 0, shp.prod, shp.nib, pl.cls[cls])) continue;
-      fill_table(L, pl);
-      rc = install_plan(c, pl);
-      if (!rc) rc = hip_rc(hipMemcpyAsync(c->ws, snap.data(), c->lo.o_wg, hipMemcpyHostToDevice, c->stream));
-      if (!rc) rc = hip_rc(hipMemcpyAsync(c->ws + L.o_ist, snap.data() + L.o_ist, L.total - L.o_ist,
-                                          hipMemcpyHostToDevice, c->stream));
-      if (!rc) rc = hip_rc(hipEventRecord(e0, c->stream));
-      // the classes run side by side, so time all of them with this
-      // candidate for `cls` and the best pages found so far for the others
-      for (int r = 0; r < repeats && !rc; ++r) rc = hip_rc(enqueue_sweeps(c, flips));
-      if (!rc) rc = hip_rc(hipEventRecord(e1, c->stream));
-      if (!rc) rc = sync(c);
-      float ms = 0.0f;
-      if (!rc) rc = hip_rc(hipEventElapsedTime(&ms, e0, e1));
-      if (rc) break;
-      // every candidate runs the same walkers for the same attempts
-      const float per = ms;
-      if (best_ms < 0.0f || per < best_ms) {
-        best_ms = per;
-        best.cls[cls] = pl.cls[cls];
+    pmin_all = std::min(pmin_all, pmin);
+    pmax_all = std::max(pmax_all, pmax);
+  }
+  for (int p = pmin_all; p <= pmax_all && !rc; p <<= 1)
+    for (int prod = 0; prod < 2 && !rc; ++prod)
+      for (int nib = 0; nib < (L.nib_ok[2] ? 2 : 1) && !rc; ++nib) {
+        LaunchPlan pl = c->plan;
+        bool ok = true;
+        for (int cls = 0; cls < 3 && ok; ++cls) {
+          if (L.walkers[cls] == 0) continue;
+          int pmin, pmax;
+          page_range(L, cls, pmin, pmax);
+          const int pc = std::min(std::max(p, pmin), pmax);
+          ok = plan_class(L, cls, budget, pc, 0, prod, cls == 2 ? nib : 0, pl.cls[cls]) == 0;
+        }
+        if (ok) rc = consider(pl);
       }
-    }
+  // Then coordinate descent, two passes over the classes: every shape of
+  // one class with the others at their best so far.
+  for (int step = 0; step < 6 && !rc; ++step) {
+    const int cls = step % 3;
+    if (L.walkers[cls] == 0) continue;
+    int pmin, pmax;
+    page_range(L, cls, pmin, pmax);
+    for (int p = pmin; p <= pmax && !rc; p <<= 1)
+      for (int prod = 0; prod < 2 && !rc; ++prod)
+        for (int nib = 0; nib < (cls == 2 && L.nib_ok[cls] ? 2 : 1) && !rc; ++nib) {
+          LaunchPlan pl = best;
+          if (plan_class(L, cls, budget, p, 0, prod, nib, pl.cls[cls])) continue;
+          rc = consider(pl);
+        }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -321,20 +321,23 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
       // bin + M - PM is the lowest page start that still covers bin + M,
       // bin - M the highest that covers bin - M (PM >= 2M); the start then
       // stays inside [lo, hi - PM].  Both are integer medians.
-      const int top = base + PM;
       const int nbase = med3_i32(med3_i32(base, bin + m_pm, bin - M), lo, hi_pm);
       const int sft = nbase - base;  // -D..D
       const bool up = sft > 0;
       const int shn = up ? sft : -sft;
+      // up: bins base, base+1, .. leave and the bins PG above them enter;
+      // down: bins base+PM, base+PM-1, .. leave and the bins PG below them enter --
+      // each pair shares a slot.  A frozen walker writes back its unchanged
+      // ln g and no H increments.
+      const int stp = up ? 1 : -1;
+      const int ev0 = up ? base : base + PM;
+      const int dpg = __mul24(stp, PG);
 #pragma unroll
       for (int i = 0; i < DMAX; ++i) {
         if (i < shn) {
-          // up: bin base+i leaves, base+i+PG enters; down: top-i leaves,
-          // top-i-PG enters -- the same slot.  A frozen walker writes back
-          // its unchanged ln g and no H increments.
-          const int ev = up ? base + i : top - i;
+          const int ev = ev0 + i * stp;
           const uint32_t e = eoff + (uint32_t)ev;
-          const uint32_t en = up ? e + (uint32_t)PG : e - (uint32_t)PG;
+          const uint32_t en = e + (uint32_t)dpg;
           const int j = prow(ev & PM);
           if (PREC == kFP64) {
             *at_off(lngw, e << 3) = plg[j];
@@ -388,7 +391,9 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
       const uint32_t aw = __mul24((uint32_t)y, (uint32_t)S4) + (uint32_t)lane4;
       const uint32_t ad = __mul24((uint32_t)((y + 1) & 31), (uint32_t)S4) + (uint32_t)lane4;
       const uint32_t au = __mul24((uint32_t)((y - 1) & 31), (uint32_t)S4) + (uint32_t)lane4;
-      const uint32_t wrow = *reinterpret_cast<const uint32_t*>(lds + aw);
+      uint32_t awk = aw;
+      asm volatile("" : "+v"(awk));  // keep the address for the write-back
+      const uint32_t wrow = *reinterpret_cast<const uint32_t*>(lds + awk);
       const uint32_t wd = *reinterpret_cast<const uint32_t*>(lds + ad);
       const uint32_t wu = *reinterpret_cast<const uint32_t*>(lds + au);
       __builtin_amdgcn_sched_barrier(0);
@@ -404,7 +409,7 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
       const uint32_t vd = ~(wd ^ wrow) & fm;   // lower neighbour agrees
       const uint32_t vu = ~(wu ^ wrow) & fm;   // upper neighbour agrees
       const int bn = bin - 2 + __builtin_popcount(hz) + __builtin_popcount(vd) + __builtin_popcount(vu);
-      complete(r, rn, bn, 0, aw, wrow, fm, site, nbt);
+      complete(r, rn, bn, 0, awk, wrow, fm, site, nbt);
       return;
     }
     int y, x, xr, xl, yd, yu;
