@@ -29,6 +29,11 @@ SMALL = {
                                     flips=1000, seed=4),
     "ising_L40_h6_m2_tworow": WL.config(WL.ISING, 40, n_windows=6, walkers_per_window=2,
                                         flips=3000, seed=8),
+    # L = 32: one word per row, neighbours by word rotation (its own loop copy)
+    "ising_L32_h4_m2": WL.config(WL.ISING, 32, n_windows=4, walkers_per_window=2, flips=1000,
+                                 seed=14),
+    "ising_L32_h3_m3_fp32c": WL.config(WL.ISING, 32, n_windows=3, walkers_per_window=3,
+                                       flips=800, seed=15, precision=WL.FP32C),
     "potts_q2_L8_h3_m2": WL.config(WL.POTTS, 8, q=2, n_windows=3, walkers_per_window=2,
                                    flips=700, seed=5),
     "potts_q3_L10_h6_m3": WL.config(WL.POTTS, 10, q=3, n_windows=6, walkers_per_window=3,
@@ -225,6 +230,8 @@ def test_unreachable_window_is_reported_on_both_sides():
     ("potts_q10_L8_h4_m4", 32, 3, 0, 1),
     ("potts_q20_L7_h3_m2", 32, 0, 0, 1),
     ("ising_L40_h6_m2_tworow", 16, 0, 1, -1),
+    ("ising_L32_h4_m2", 16, 5, 0, -1), ("ising_L32_h4_m2", 16, 0, 1, -1),
+    ("ising_L32_h4_m2", 1024, 3, 0, -1), ("ising_L32_h3_m3_fp32c", 16, 7, 1, -1),
     ("ising_L8_fp32c", 16, 0, 1, -1),
     ("potts_q10_L8_fp32c", 32, 7, 0, 1), ("potts_q10_L8_fp32c", 32, 0, 1, 0)])
 def test_page_size_and_group_shape_do_not_change_results(name, page, group, prod, nib):
