@@ -496,10 +496,22 @@ def alu_rate(iters=4096):
     forms = ["v_xad_u32", "v_mad_u64_u32 + v_xor_b32", "v_mul_lo_u32 + v_mul_hi_u32 + v_xor_b32",
              "v_fma_f64", "v_bitop3_b32"]
     one = ns[0]
-    return {"metric": "VALU issue cost per wavefront step, 8 waves per SIMD",
+    clock_ghz = 4.0 / one
+    lib.lds_rate.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_int32]
+    lib.lds_rate.restype = ctypes.c_int
+    lds = (ctypes.c_double * 3)()
+    rc = lib.lds_rate(iters, lds, 3)
+    if rc != 0:
+        raise RuntimeError(f"lds_rate failed ({rc})")
+    lforms = ["4 B per lane (ds_read2st64_b32)", "8 B per lane (ds_read2st64_b64)",
+              "16 B per lane (ds_read_b128)"]
+    return {"metric": "VALU issue cost per wavefront step, 8 waves per SIMD; LDS read bandwidth",
             "ns_per_wave_step": dict(zip(forms, ns)),
             "slots": dict(zip(forms, [v / one for v in ns])),
-            "clock_ghz_if_one_slot_is_4_cycles": 4.0 / one}
+            "clock_ghz_if_one_slot_is_4_cycles": clock_ghz,
+            "lds_read_TBps": dict(zip(lforms, [v / 1e12 for v in lds])),
+            "lds_read_B_per_clk_per_cu_at_that_clock":
+                dict(zip(lforms, [v / (N_CU * clock_ghz * 1e9) for v in lds]))}
 
 
 def main():
