@@ -260,15 +260,19 @@ def test_page_size_and_group_shape_do_not_change_results(name, page, group, prod
         compare_state(ctx, 0, sim)
 
 
-@pytest.mark.parametrize("cfg_name,replicas,sample", [("ISING_L32", 0, (0, 1, -1)),
-                                                      ("POTTS_Q10_L20", 3, (0, 2)),
-                                                      ("POTTS_Q10_L20_FP32C", 2, (1,))])
-def test_full_size_configs_sampled(cfg_name, replicas, sample):
-    """Full-size workloads in the launch shape the benchmark uses; sampled
-    instances are checked walker by walker against the oracle."""
+@pytest.mark.parametrize("cfg_name,replicas,sample,page,nib", [
+    ("ISING_L32", 0, (0, 1, -1), 16, -1),
+    ("POTTS_Q10_L20", 3, (0, 2), 32, 1),
+    ("POTTS_Q10_L20_FP32C", 2, (1,), 32, 1)])
+def test_full_size_configs_sampled(cfg_name, replicas, sample, page, nib):
+    """Full-size workloads in the launch shape the benchmark's autotuner
+    picks (page bins, Potts nibbles, no RNG producer); sampled instances are
+    checked walker by walker against the oracle."""
     cfg = getattr(WL, cfg_name)
     R = replicas or WL.bench_replicas(cfg)
     ctx = gpu_context([cfg] * R)
+    plan = ctx.set_launch(page_bins=page, rng_producer=0, potts_nibbles=nib)
+    print(f"[parity] {cfg_name} x{R}: plan {plan}", flush=True)
     F = cfg["flips_per_exchange"]
     cycles = 2
     ctx.run_cycles(cycles, F)
