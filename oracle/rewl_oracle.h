@@ -29,6 +29,13 @@
  * flatness mask, merge order, exchange pairing, normalisation) are fixed
  * where each is implemented, and the comments there state the choice.
  *
+ * Every function here is pinned by the tests against results that do not
+ * come from this file: brute-force enumeration, exact densities of states
+ * (transfer matrix, Kaufman's torus formula), closed forms, invariants and
+ * planted mistakes.  One quantity has no exact reference: ln g of q >= 3
+ * Potts beyond L = 4, checked only statistically (sum rule, exact
+ * low-energy counts) -- parity unpinned for that quantity.
+ *
  * Error convention: functions returning int give 0 on success and a negative
  * value on error; orc_new returns NULL on invalid parameters.
  */
