@@ -683,7 +683,7 @@ int rewl_autotune(rewl_ctx* c, int64_t flips, int32_t repeats, int32_t* out) {
   }
   for (int p = pmin_all; p <= pmax_all && !rc; p <<= 1)
     for (int prod = 0; prod < 2 && !rc; ++prod)
-      for (int nib = 0; nib < (L.nib_ok[2] ? 2 : 1) && !rc; ++nib) {
+      for (int nib = 0; nib < (L.walkers[2] > 0 && L.nib_ok[2] ? 2 : 1) && !rc; ++nib) {
         LaunchPlan pl = c->plan;
         bool ok = true;
         for (int cls = 0; cls < 3 && ok; ++cls) {
