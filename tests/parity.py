@@ -1,5 +1,8 @@
 """Helpers for GPU-vs-oracle parity tests: build the same REWL instance on
 both sides and compare their complete logical state."""
+import math
+import os
+
 import numpy as np
 
 from oracle import oracle as O
@@ -73,3 +76,24 @@ def compare_state(ctx, instance, sim, slots=None, windows=True):
     t, r, a = ctx.get_exchange_stats(instance)
     ot, orr, oa = sim.exchange_stats()
     assert np.array_equal(t, ot) and np.array_equal(r, orr) and np.array_equal(a, oa)
+
+
+GOLDEN_ISING_L32_RUN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                    "oracle_ising_L32_h16_m8_seed1.txt")
+
+
+def load_golden_ising_L32_run():
+    """The stored oracle run: metadata (done_merge, cycles, joins) and the
+    joined and normalised ln g per bin."""
+    meta, raw, norm = {}, [], []
+    with open(GOLDEN_ISING_L32_RUN) as f:
+        for line in f:
+            if line.startswith("#"):
+                parts = line[1:].split()
+                if parts and parts[0] in ("done_merge", "cycles", "joins"):
+                    meta[parts[0]] = [int(p) for p in parts[1:]]
+                continue
+            a, b = line.split()
+            raw.append(-math.inf if a == "-inf" else float.fromhex(a))
+            norm.append(-math.inf if b == "-inf" else float.fromhex(b))
+    return meta, np.array(raw), np.array(norm)
