@@ -3,7 +3,8 @@
 // Each workgroup is one 64-lane wavefront holding up to 64 walkers of one
 // instance.  For the duration of a launch every walker keeps in LDS
 //   * its lattice: Ising spins as bit rows (one 32-bit word per row for
-//     L <= 32, two for L <= 64), Potts spins as bytes;
+//     L <= 32, two for L <= 64), Potts spins as 4-bit nibbles (q <= 16) or
+//     bytes;
 //   * a page of PG = 2^k bins of its ln g window, direct-mapped (bin b lives
 //     in slot b mod PG), with the histogram increments H gathered since the
 //     launch began.  Walkers move at most D bins per attempt (D = 2 for
@@ -13,8 +14,10 @@
 //     stored, its H increments added to the histogram in device memory) and
 //     the bin that enters shares its slot; the entering ln g is loaded into
 //     registers and committed one attempt later, since it cannot be reached
-//     before then, so the wave never waits for device memory inside the
-//     loop.  Windows of at most PG bins live in LDS entirely.
+//     before then, so the load has a whole attempt to arrive.  Windows of
+//     at most PG bins live in LDS entirely.
+// Three compile-time copies of the attempt loop serve any L, L a power of
+// two, and Ising L = 32 (one word per row, neighbours by word rotation).
 // LDS is interleaved by lane: element e of lane l sits at e * S + l (S =
 // lanes per workgroup), so the 32-bit words that one instruction touches
 // across the wavefront fall into consecutive banks.  Random numbers come
