@@ -78,3 +78,19 @@ def test_reserved_parameter_field_must_be_zero():
 def test_one_over_t_configs_lay_out():
     cfg = dict(workloads.ISING_L32, schedule=workloads.ONE_OVER_T, walkers_per_window=64)
     assert rewl.rewl_workspace_bytes([workloads.rewl_params_of(cfg)]) > 0
+
+
+def test_measurement_probe_library_exports_its_entry_points():
+    """libalurate.so (the VALU issue-cost and LDS-bandwidth probe behind the
+    sweep's roofline) is built beside librewl.so and exports both calls;
+    bad arguments are rejected before any GPU work."""
+    path = os.path.join(os.path.dirname(rewl.__file__), "libalurate.so")
+    lib = C.CDLL(path)
+    for name in ("alu_rate", "lds_rate"):
+        fn = getattr(lib, name)
+        fn.argtypes = [C.c_int32, C.POINTER(C.c_double), C.c_int32]
+        fn.restype = C.c_int
+        out = (C.c_double * 5)()
+        assert fn(0, out, 5) == -1
+        assert fn(16, None, 5) == -1
+        assert fn(16, out, 1) == -1
