@@ -18,7 +18,7 @@
  *           window reached f_final.
  *   Sec. 3  the h pieces are joined where the slopes d ln g/dE agree best
  *           (Eq. 2), using a 5-point derivative (Fig. 2).
- *   Sec. 5  Eqs. (5)-(6): <E> and C_V from g(E).
+ *   Sec. 5  Eqs. (7)-(8): <E> and C_V from g(E).
  *
  * Models: 2D Ising (E = -sum s_i s_j, s = +-1) and q-state Potts
  * (E = -sum delta(s_i, s_j)) on a periodic L x L lattice, single-site moves.
@@ -252,7 +252,7 @@ int rewl_get_piece(rewl_ctx* ctx, int32_t instance, int32_t slot, double* host_l
 int rewl_jackknife(rewl_ctx* ctx, int32_t instance, double* host_mean, double* host_err,
                    int32_t capacity, int32_t* n_bins_out);
 
-/* Synchronises.  Canonical <E> and C_V (Eqs. 5-6, k_B = 1) from the joined,
+/* Synchronises.  Canonical <E> and C_V (Sec. 5, Eqs. 7-8, k_B = 1) from the joined,
  * normalised ln g of an instance, evaluated on the GPU in FP64 for nT
  * temperatures.  Errors: INVAL, HIP. */
 int rewl_thermo(rewl_ctx* ctx, int32_t instance, const double* T, int32_t nT,

@@ -2,7 +2,7 @@
 
 The oracle is a plain single-threaded C implementation of replica-exchange
 Wang-Landau sampling written from the paper (arXiv:1402.2328, Secs. 2-3 and
-Eqs. 1-2, 5-6).  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU
+Eqs. 1-2, 7-8).  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU
 baseline leg of ``bench.py`` may import this module.
 """
 import ctypes as C
@@ -76,6 +76,8 @@ def lib():
         L.orc_exp_spec.argtypes = [C.c_double]
         L.orc_expf_spec.restype = C.c_float
         L.orc_expf_spec.argtypes = [C.c_float]
+        L.orc_exchange_pairing.argtypes = [C.c_uint64, C.c_int32, C.c_uint64, C.c_int32,
+                                           C.c_int32, P]
         L.orc_accept64.argtypes = [C.c_uint64, C.c_double]
         L.orc_accept32.argtypes = [C.c_uint32, C.c_float]
         L.orc_energy.restype = C.c_int32
@@ -226,6 +228,15 @@ def philox(ctr, key):
     o = np.zeros(4, np.uint32)
     lib().orc_philox4x32_10(_p(c), _p(k), _p(o))
     return o
+
+
+def exchange_pairing(seed, instance, rnd, w, m):
+    """Permutation pi of 0..m-1: walker k of window w meets walker pi[k] of
+    window w+1 in exchange round `rnd`."""
+    pi = np.zeros(m, np.int32)
+    if lib().orc_exchange_pairing(int(seed), int(instance), int(rnd), int(w), int(m), _p(pi)):
+        raise ValueError("bad pairing arguments")
+    return pi
 
 
 def exp_spec(x):

@@ -620,21 +620,42 @@ static double lng_at(const orc_sim* s, int slot, int j) {
  * without looking at energies; a pair with an energy outside the other
  * window is disregarded; otherwise accept with
  * min[1, g_i(E_X)/g_i(E_Y) * g_j(E_Y)/g_j(E_X)] and swap configurations. */
+/* Partner choice of Sec. 2 (a walker picks a random partner in the
+ * neighbouring window): a uniformly random permutation pi of 0..m-1 by the
+ * Fisher-Yates shuffle.  For i = m-1 down to 1, j is uniform in 0..i,
+ * j = (r (i+1)) >> 32 with r the next 32-bit word of the EXCH_PERM stream
+ * (counter: round, (w << 8) | call, instance tag; four words per call), and
+ * pi[i], pi[j] are swapped.  Walker k of window w meets walker pi[k] of
+ * window w+1. */
+int orc_exchange_pairing(uint64_t seed, int32_t instance, uint64_t round, int32_t w, int32_t m,
+                         int32_t* pi) {
+  if (!pi || m < 1 || w < 0 || instance < 0) return -1;
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  for (int k = 0; k < m; ++k) pi[k] = k;
+  uint32_t r[4];
+  int used = 4, call = 0;
+  for (int i = m - 1; i >= 1; --i) {
+    if (used == 4) {
+      uint32_t ctr[4] = {(uint32_t)round, (uint32_t)(round >> 32), ((uint32_t)w << 8) | (uint32_t)call++,
+                         TAG_PERM | ((uint32_t)instance << 8)};
+      orc_philox4x32_10(ctr, key, r);
+      used = 0;
+    }
+    int j = (int)(((uint64_t)r[used++] * (uint32_t)(i + 1)) >> 32);
+    int32_t tmp = pi[i]; pi[i] = pi[j]; pi[j] = tmp;
+  }
+  return 0;
+}
+
 int orc_exchange(orc_sim* s) {
   if (!s) return -1;
   if (s->done) return 0;
   int m = s->m;
   uint64_t t = s->rounds;
-  int* pi = (int*)xcalloc(m, sizeof(int));
+  int32_t* pi = (int32_t*)xcalloc(m, sizeof(int32_t));
   for (int w = (int)(t & 1); w + 1 < s->h; w += 2) {
-    for (int k = 0; k < m; ++k) pi[k] = k;
     uint32_t r[4];
-    int used = 4, call = 0;
-    for (int i = m - 1; i >= 1; --i) {
-      if (used == 4) { draw(s, t, ((uint32_t)w << 8) | (uint32_t)call++, TAG_PERM, r); used = 0; }
-      int j = (int)(((uint64_t)r[used++] * (uint32_t)(i + 1)) >> 32);
-      int tmp = pi[i]; pi[i] = pi[j]; pi[j] = tmp;
-    }
+    orc_exchange_pairing(s->p.seed, s->p.instance, t, w, m, pi);
     for (int k = 0; k < m; ++k) {
       int si = w * m + k, sj = (w + 1) * m + pi[k];
       int bx = bin_of(s, s->E[si]), by = bin_of(s, s->E[sj]);
@@ -892,7 +913,7 @@ int orc_join(const orc_sim* s, double* out, int32_t* joins) {
   return orc_normalise(s->model, s->N, s->q, s->nbins, out);
 }
 
-/* Canonical averages from g(E) (Eqs. 5-6, k_B = 1): weights
+/* Canonical averages from g(E) (Sec. 5, Eqs. 7-8, k_B = 1): weights
  * g(E) exp(-E/T) by log-sum-exp, variance by a second pass. */
 int orc_thermo(const double* lng, int32_t nbins, int32_t emin, int32_t binw,
                const double* T, int32_t nT, double* Emean, double* Cv) {

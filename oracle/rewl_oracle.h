@@ -24,7 +24,7 @@
  *   Sec. 2, the "1/t" rule named as compatible with REWL: ln f halves while
  *           every walker visits every level, then follows 1/t.
  *   Sec. 3, statistical errors by the jackknife over the m pieces per window.
- *   Sec. 5, Eqs. (5)-(6): <E>, C_V from g(E).
+ *   Sec. 5, Eqs. (7)-(8): <E>, C_V from g(E).
  * Points the paper leaves open (window edges, RNG streams, warm-up,
  * flatness mask, merge order, exchange pairing, normalisation) are fixed
  * where each is implemented, and the comments there state the choice.
@@ -137,6 +137,11 @@ int orc_join_raw(const orc_sim* s, double* out, int32_t* joins);
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 double orc_exp_spec(double x);          /* x in [-40, 0) */
 float orc_expf_spec(float x);           /* x in [-17, 0) */
+/* Exchange partners of round `round` between windows w and w+1 (Sec. 2):
+ * pi (m entries) receives a uniform random permutation; walker k of window
+ * w is paired with walker pi[k] of window w+1. */
+int orc_exchange_pairing(uint64_t seed, int32_t instance, uint64_t round, int32_t w, int32_t m,
+                         int32_t* pi);
 int orc_accept64(uint64_t u53, double delta);
 int orc_accept32(uint32_t u24, float delta);
 int32_t orc_energy(int32_t model, int32_t L, int32_t q, const int8_t* spins);

@@ -248,9 +248,10 @@ void page_range(const Layout& Lo, int cls, int& pmin, int& pmax) {
 }
 
 // LDS bytes of a workgroup of G walkers with page P; with a producer the
-// RNG double buffer and a flag word follow the page.
+// RNG double buffer (16-byte aligned) and a flag word follow the page.
 size_t lds_of(int lat, int G, int P, int prod) {
-  return (size_t)G * (lat + 12 * P) + (prod ? (size_t)2 * kRngChunk * G * 16 + 16 : 0);
+  const size_t page_end = (size_t)G * (lat + 12 * P);
+  return prod ? align_up(page_end, 16) + (size_t)2 * kRngChunk * G * 16 + 16 : page_end;
 }
 
 int n_compute_units() {

@@ -5,7 +5,7 @@
 // and the in-window average), k_merge_finish, k_exchange (Eq. 1, swaps
 // configuration indices, never lattice data), k_exchange_finish.  End of
 // run: k_join (Sec. 3 joining + normalisation in FP64), k_jackknife
-// (error bars from the m pieces per window) and k_thermo (Eqs. 5-6).
+// (error bars from the m pieces per window) and k_thermo (Sec. 5, Eqs. 7-8).
 #include <float.h>
 #include <math.h>
 
@@ -148,11 +148,16 @@ __global__ __launch_bounds__(256) void k_merge_windows(DevPtrs P) {
   const int tid = threadIdx.x;
   uint8_t* U = P.U + W.u_base;
 
+  // visited union; every walker's H is read here at every check, so the
+  // 2^31 guard on the histogram counters sits in this loop
   uint64_t cnt = 0;
   for (int j = tid; j < nb; j += blockDim.x) {
     uint8_t u = U[j];
-    for (int k = 0; k < m; ++k)
-      if (P.H[W.lng_base + (int64_t)k * nb + j] > 0) u = 1;
+    for (int k = 0; k < m; ++k) {
+      const uint32_t h = P.H[W.lng_base + (int64_t)k * nb + j];
+      if (h > 0) u = 1;
+      if (h >= 0x80000000u) atomicMin(&P.ist[W.inst].error, -5);
+    }
     U[j] = u;
     cnt += u;
   }
@@ -166,7 +171,6 @@ __global__ __launch_bounds__(256) void k_merge_windows(DevPtrs P) {
       const uint64_t h = P.H[W.lng_base + (int64_t)k * nb + j];
       sm += h;
       if (U[j] && h < mn) mn = h;
-      if (h >= 0x80000000u) atomicMin(&P.ist[W.inst].error, -5);
     }
     mn = block_reduce(mn, [](uint64_t a, uint64_t b) { return a < b ? a : b; }, red64);
     sm = block_reduce(sm, [](uint64_t a, uint64_t b) { return a + b; }, red64);
@@ -555,7 +559,7 @@ __global__ __launch_bounds__(256) void k_jackknife(DevPtrs P, int32_t instance) 
   }
 }
 
-// Canonical <E> and C_V (Eqs. 5-6) from the joined ln g: one thread per T.
+// Canonical <E> and C_V (Sec. 5, Eqs. 7-8) from the joined ln g: one thread per T.
 __global__ void k_thermo(DevPtrs P, int32_t instance, int32_t nT) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nT) return;

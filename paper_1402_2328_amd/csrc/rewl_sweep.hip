@@ -63,8 +63,9 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
   const int PM = PG - 1;
   const int tid = threadIdx.x;
   const int lane = tid & (kSweepWave - 1);
-  // RNG double buffer [2][kRngChunk][S] after the page, then a flag word
-  uint4* rbuf = reinterpret_cast<uint4*>(lds + (size_t)4 * NWL * S + (size_t)12 * PG * S);
+  // RNG double buffer [2][kRngChunk][S] after the page, at the next 16-byte
+  // boundary (its reads are 16 bytes wide), then a flag word
+  uint4* rbuf = reinterpret_cast<uint4*>(lds + (((size_t)4 * NWL * S + (size_t)12 * PG * S + 15) & ~(size_t)15));
   bool skip = P.ist[wg.inst].done || P.ist[wg.inst].error;
   if (PROD) {
     // one decision for both wavefronts: both must reach every barrier

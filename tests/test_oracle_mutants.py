@@ -1,8 +1,8 @@
 """Planted mistakes in a copy of the oracle must be caught by its pins (CPU).
 
 Each case edits one line of a temporary copy of ``oracle/rewl_oracle.c`` (a
-swapped operand, a wrong sign, a dropped term, an update at the wrong bin),
-builds it, and runs one pin test against it in a subprocess.  The pin must
+swapped operand, a wrong sign, a dropped term, an update at the wrong bin,
+an off-by-one in the exchange shuffle), builds it, and runs one pin test against it in a subprocess.  The pin must
 fail; if it passed, the pin would not be able to tell the oracle from a
 plausible wrong implementation.
 """
@@ -69,6 +69,18 @@ MUTANTS = [
      "s->pieces[w * m + k][j] = lng_at(s, w * m + k, j);",
      "s->pieces[w * m + k][j] = lng_at(s, w * m, j);",
      "tests/test_oracle_schedule.py::test_pieces_are_the_walkers_before_the_freezing_merge"),
+    ("pairing_sattolo",
+     "int j = (int)(((uint64_t)r[used++] * (uint32_t)(i + 1)) >> 32);",
+     "int j = (int)(((uint64_t)r[used++] * (uint32_t)i) >> 32);",
+     "tests/test_oracle_pairing.py::test_pairing_is_uniform_over_all_permutations"),
+    ("pairing_last_swap_skipped",
+     "for (int i = m - 1; i >= 1; --i) {\n    if (used == 4) {",
+     "for (int i = m - 1; i >= 2; --i) {\n    if (used == 4) {",
+     "tests/test_oracle_pairing.py::test_pairing_is_uniform_over_all_permutations"),
+    ("exchange_partner_not_permuted",
+     "int si = w * m + k, sj = (w + 1) * m + pi[k];",
+     "int si = w * m + k, sj = (w + 1) * m + k;",
+     "tests/test_oracle_pairing.py::test_exchange_round_pairs_walkers_by_the_pairing"),
     ("energy_neighbour_index",
      "int sd = sp[((y + 1) % L) * L + x];",
      "int sd = sp[((y + 1) % L) * L + (x + 1) % L];",

@@ -5,7 +5,7 @@ mathematics: convergence to exact densities of states (brute force, Kaufman),
 Potts sum rules and low-energy counts, the stationary distribution implied by
 detailed balance for fixed ln g (WL acceptance and exchange Eq. 1 together),
 bookkeeping invariants, exact recovery by the joining procedure (Eq. 2) and
-canonical averages (Eqs. 5-6) against direct high-precision sums.
+canonical averages (Sec. 5, Eqs. 7-8) against direct high-precision sums.
 """
 import math
 
