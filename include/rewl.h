@@ -221,6 +221,14 @@ int rewl_get_geometry(rewl_ctx* ctx, int32_t instance, int32_t* N, int32_t* nbin
 int rewl_get_walker(rewl_ctx* ctx, int32_t instance, int32_t slot, int8_t* spins,
                     int32_t* energy, uint32_t* H, double* lng, uint64_t* attempts,
                     int32_t* config_id);
+/* Host only.  Where a walker's state sits in the workspace (byte offsets
+ * from its start): its energy (one int32), its histogram row (n_bins uint32)
+ * and its ln g row (n_bins FP64, or for FP32C the n_bins floats of the high
+ * parts).  For inspection tools and tests that inject faults (a non-finite
+ * ln g, a histogram near 2^31, an energy outside the window); the layout is
+ * otherwise private.  Any pointer may be NULL.  Errors: INVAL. */
+int rewl_locate_walker(rewl_ctx* ctx, int32_t instance, int32_t slot, size_t* energy_off,
+                       size_t* H_off, size_t* lng_off, int32_t* n_bins);
 /* FP32C only: the two-float parts of a walker's ln g. */
 int rewl_get_walker_f32(rewl_ctx* ctx, int32_t instance, int32_t slot, float* hi, float* lo);
 /* Synchronises.  Visited-union mask of a window (nb_w bytes). */

@@ -876,6 +876,21 @@ int rewl_get_walker(rewl_ctx* c, int32_t instance, int32_t slot, int8_t* spins, 
   return rc;
 }
 
+int rewl_locate_walker(rewl_ctx* c, int32_t instance, int32_t slot, size_t* energy_off,
+                       size_t* H_off, size_t* lng_off, int32_t* n_bins) {
+  if (!c || instance < 0 || instance >= (int32_t)c->lo.inst.size()) return REWL_E_INVAL;
+  const InstDesc& I = c->lo.inst[instance];
+  if (slot < 0 || slot >= I.W) return REWL_E_INVAL;
+  const Layout& L = c->lo;
+  const WinDesc& W = L.win[I.win_base + slot / I.m];
+  const size_t row = (size_t)(W.lng_base + (int64_t)(slot % I.m) * W.nb);
+  if (energy_off) *energy_off = L.o_E + sizeof(int32_t) * (size_t)(I.slot_base + slot);
+  if (H_off) *H_off = L.o_H + sizeof(uint32_t) * row;
+  if (lng_off) *lng_off = L.prec == REWL_FP64 ? L.o_lng + sizeof(double) * row : L.o_lhi + sizeof(float) * row;
+  if (n_bins) *n_bins = W.nb;
+  return REWL_OK;
+}
+
 int rewl_get_walker_f32(rewl_ctx* c, int32_t instance, int32_t slot, float* hi, float* lo) {
   if (!c || instance < 0 || instance >= (int32_t)c->lo.inst.size()) return REWL_E_INVAL;
   if (c->lo.prec != REWL_FP32C) return REWL_E_STATE;
@@ -959,7 +974,7 @@ int rewl_jackknife(rewl_ctx* c, int32_t instance, double* mean, double* err, int
   int rc = d2h(c, &st, c->P.ist + instance, 1);
   if (rc) return rc;
   if (!st.done) return REWL_E_STATE;
-  rc = hip_rc(launch_jackknife(c->P, instance, c->stream));
+  rc = hip_rc(launch_jackknife(c->P, instance, c->P.rep + I.rep_base, c->P.jk, c->stream));
   if (!rc) rc = d2h(c, mean, c->P.jk + (int64_t)I.m * I.nbins, (size_t)I.nbins);
   if (!rc) rc = d2h(c, err, c->P.jk + (int64_t)(I.m + 1) * I.nbins, (size_t)I.nbins);
   return rc;

@@ -246,15 +246,15 @@ __device__ __forceinline__ T wave_reduce(T v, Op op) {
 }
 
 template <typename T, typename Op>
-__device__ T block_reduce(T v, Op op, T* scratch) {
+__device__ T block_reduce(T v, Op op, T* red) {
   v = wave_reduce(v, op);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nw = (blockDim.x + 63) >> 6;
   __syncthreads();
-  if (lane == 0) scratch[wave] = v;
+  if (lane == 0) red[wave] = v;
   __syncthreads();
-  T r = scratch[0];
-  for (int i = 1; i < nw; ++i) r = op(r, scratch[i]);
+  T r = red[0];
+  for (int i = 1; i < nw; ++i) r = op(r, red[i]);
   __syncthreads();
   return r;
 }

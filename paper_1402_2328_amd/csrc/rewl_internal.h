@@ -111,9 +111,11 @@ hipError_t launch_sweep_class(const DevPtrs& P, int cls, SweepShape sh, int32_t 
 hipError_t launch_merge(const DevPtrs& P, hipStream_t s);
 hipError_t launch_exchange(const DevPtrs& P, hipStream_t s);
 hipError_t launch_join(const DevPtrs& P, int32_t instance, int32_t normalise, hipStream_t s);
-// Leave-one-out joins of an instance's frozen pieces; mean and error land
-// in rows m and m + 1 of P.jk.
-hipError_t launch_jackknife(const DevPtrs& P, int32_t instance, hipStream_t s);
+// Leave-one-out joins of an instance's frozen pieces, with the instance's
+// window representatives in rep (sum of its window sizes) and the rows in jk
+// ((m + 2) x nbins); mean and error land in rows m and m + 1.
+hipError_t launch_jackknife(const DevPtrs& P, int32_t instance, double* rep, double* jk,
+                            hipStream_t s);
 hipError_t launch_thermo(const DevPtrs& P, int32_t instance, int32_t nT, hipStream_t s);
 hipError_t prepare_sweep_lds(size_t lds_bytes);
 

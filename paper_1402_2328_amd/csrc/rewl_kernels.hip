@@ -364,14 +364,16 @@ __device__ __forceinline__ double beta5(const double* l, int j) {
   return (((l[j - 2] - 8.0 * l[j - 1]) + 8.0 * l[j + 1]) - l[j + 2]) / 12.0;
 }
 
-// Joins the window representatives in P.rep into R (Sec. 3, Eq. 2): the
+// Joins the window representatives into R (Sec. 3, Eq. 2): the
 // first window as it is, then window w from the bin of (w-1, w) where the
 // five-point slopes agree best (lowest such bin on ties; the middle of the
 // overlap if no bin qualifies), shifted to continue the joined curve.
 // normalise: Ising sum g = 2^N, Potts g(E_min) = q.  Whole block.
-__device__ void stitch_normalise(const DevPtrs& P, const InstDesc& I, double* R, int normalise,
-                                 double* redd, int64_t* redi, double& shift_s, int& best_s,
-                                 bool record_joins) {
+// rep: this instance's representatives, window w at rep + (rep_off -
+// the instance's rep_base).
+__device__ void stitch_normalise(const DevPtrs& P, const InstDesc& I, const double* rep, double* R,
+                                 int normalise, double* redd, int64_t* redi, double& shift_s,
+                                 int& best_s, bool record_joins) {
   const int tid = threadIdx.x, nt = blockDim.x;
   __syncthreads();
   for (int b = tid; b < I.nbins; b += nt) R[b] = -INFINITY;
@@ -379,7 +381,7 @@ __device__ void stitch_normalise(const DevPtrs& P, const InstDesc& I, double* R,
   {
     const WinDesc W0 = P.win[I.win_base];
     const uint8_t* U0 = P.U + W0.u_base;
-    const double* r0 = P.rep + W0.rep_off;
+    const double* r0 = rep + (W0.rep_off - I.rep_base);
     for (int j = tid; j < W0.nb; j += nt) R[W0.lo + j] = U0[j] ? r0[j] : -INFINITY;
   }
   if (tid == 0) shift_s = 0.0;
@@ -387,8 +389,8 @@ __device__ void stitch_normalise(const DevPtrs& P, const InstDesc& I, double* R,
   for (int w = 1; w < I.h; ++w) {
     const WinDesc Wa = P.win[I.win_base + w - 1];
     const WinDesc Wb = P.win[I.win_base + w];
-    const double* la = P.rep + Wa.rep_off;
-    const double* lb = P.rep + Wb.rep_off;
+    const double* la = rep + (Wa.rep_off - I.rep_base);
+    const double* lb = rep + (Wb.rep_off - I.rep_base);
     const uint8_t* Ua = P.U + Wa.u_base;
     const uint8_t* Ub = P.U + Wb.u_base;
     double bestd = INFINITY;
@@ -497,15 +499,18 @@ __global__ __launch_bounds__(256) void k_join(DevPtrs P, int32_t instance, int32
       }
     }
   }
-  stitch_normalise(P, I, R, normalise, redd, redi, shift_s, best_s, true);
+  stitch_normalise(P, I, P.rep + I.rep_base, R, normalise, redd, redi, shift_s, best_s, true);
 }
 
 // Jackknife over the m pieces per window (Sec. 3): for k = 0..m-1 the
 // representatives are the pairwise means of the pieces without walker k,
-// joined and normalised into row k of P.jk; then per bin the mean of the m
+// joined and normalised into row k of jk; then per bin the mean of the m
 // rows and sqrt((m-1)/m * sum (R_k - mean)^2) go to rows m and m + 1 (-inf
-// and 0 where any row is not finite).  One block.
-__global__ __launch_bounds__(256) void k_jackknife(DevPtrs P, int32_t instance) {
+// and 0 where any row is not finite).  rep holds the instance's window
+// representatives (sum of its window sizes), jk (m + 2) x nbins doubles;
+// every element of both is written before it is read.  One block.
+__global__ __launch_bounds__(256) void k_jackknife(DevPtrs P, int32_t instance, double* rep_buf,
+                                                   double* jk) {
   __shared__ double redd[8];
   __shared__ int64_t redi[8];
   __shared__ double shift_s;
@@ -516,7 +521,7 @@ __global__ __launch_bounds__(256) void k_jackknife(DevPtrs P, int32_t instance) 
   for (int k = 0; k < m; ++k) {
     for (int w = 0; w < I.h; ++w) {
       const WinDesc W = P.win[I.win_base + w];
-      double* rep = P.rep + W.rep_off;
+      double* rep = rep_buf + (W.rep_off - I.rep_base);
       for (int j = tid; j < W.nb; j += nt) {
         double v[kMaxWalkersPerWindow];
         int n = 0;
@@ -533,14 +538,14 @@ __global__ __launch_bounds__(256) void k_jackknife(DevPtrs P, int32_t instance) 
       }
     }
     __syncthreads();
-    stitch_normalise(P, I, P.jk + (int64_t)k * nbins, 1, redd, redi, shift_s, best_s, false);
+    stitch_normalise(P, I, rep_buf, jk + (int64_t)k * nbins, 1, redd, redi, shift_s, best_s, false);
     __syncthreads();
   }
   for (int b = tid; b < nbins; b += nt) {
     bool fin = true;
     double acc = 0.0;
     for (int k = 0; k < m; ++k) {
-      const double r = P.jk[(int64_t)k * nbins + b];
+      const double r = jk[(int64_t)k * nbins + b];
       fin = fin && isfinite(r);
       acc += r;
     }
@@ -549,13 +554,13 @@ __global__ __launch_bounds__(256) void k_jackknife(DevPtrs P, int32_t instance) 
       mu = acc / (double)m;
       double v = 0.0;
       for (int k = 0; k < m; ++k) {
-        const double d = P.jk[(int64_t)k * nbins + b] - mu;
+        const double d = jk[(int64_t)k * nbins + b] - mu;
         v += d * d;
       }
       e = sqrt((double)(m - 1) / (double)m * v);
     }
-    P.jk[(int64_t)m * nbins + b] = mu;
-    P.jk[(int64_t)(m + 1) * nbins + b] = e;
+    jk[(int64_t)m * nbins + b] = mu;
+    jk[(int64_t)(m + 1) * nbins + b] = e;
   }
 }
 
@@ -618,8 +623,9 @@ hipError_t launch_join(const DevPtrs& P, int32_t instance, int32_t normalise, hi
   return hipGetLastError();
 }
 
-hipError_t launch_jackknife(const DevPtrs& P, int32_t instance, hipStream_t s) {
-  hipLaunchKernelGGL(k_jackknife, dim3(1), dim3(256), 0, s, P, instance);
+hipError_t launch_jackknife(const DevPtrs& P, int32_t instance, double* rep, double* jk,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_jackknife, dim3(1), dim3(256), 0, s, P, instance, rep, jk);
   return hipGetLastError();
 }
 

@@ -53,7 +53,7 @@ EXPORTS = ["rewl_workspace_bytes", "rewl_init", "rewl_run_sweeps", "rewl_set_lau
            "rewl_get_lng", "rewl_get_geometry", "rewl_get_walker", "rewl_get_walker_f32",
            "rewl_get_visited", "rewl_get_exchange_stats", "rewl_thermo", "rewl_checkpoint",
            "rewl_restore", "rewl_destroy", "rewl_strerror", "rewl_get_schedule",
-           "rewl_get_piece", "rewl_jackknife", "rewl_balanced_windows"]
+           "rewl_get_piece", "rewl_jackknife", "rewl_balanced_windows", "rewl_locate_walker"]
 
 
 def lib():
@@ -80,6 +80,8 @@ def lib():
     L.rewl_get_geometry.argtypes = [P, I32, P, P, P, P, P, P, P, P, P]
     L.rewl_get_walker.argtypes = [P, I32, I32, P, P, P, P, P, P]
     L.rewl_get_walker_f32.argtypes = [P, I32, I32, P, P]
+    L.rewl_locate_walker.argtypes = [P, I32, I32, C.POINTER(SZ), C.POINTER(SZ), C.POINTER(SZ),
+                                     C.POINTER(I32)]
     L.rewl_get_visited.argtypes = [P, I32, I32, P]
     L.rewl_get_exchange_stats.argtypes = [P, I32, P, P, P]
     L.rewl_thermo.argtypes = [P, I32, P, I32, P, P]
@@ -276,6 +278,14 @@ class Context:
                    "rewl_get_walker_f32")
             out["lng_hi"], out["lng_lo"] = hi, lo
         return out
+
+    def locate_walker(self, instance, slot):
+        """Byte offsets of a walker's energy, H row and ln g row in the
+        workspace, and its window's bin count."""
+        e, h, l, nb = C.c_size_t(), C.c_size_t(), C.c_size_t(), C.c_int32()
+        _check(lib().rewl_locate_walker(self._h, instance, slot, C.byref(e), C.byref(h), C.byref(l),
+                                        C.byref(nb)), "rewl_locate_walker")
+        return {"energy": e.value, "H": h.value, "lng": l.value, "n_bins": nb.value}
 
     def get_visited(self, instance, window):
         g = self.geometry[instance]

@@ -6,8 +6,7 @@ window froze, the join bins and the joined ln g; the normalised ln g within
 
 The stored run (tests/golden/oracle_ising_L32_h16_m8_seed1.txt) was written
 by tests/golden/make_oracle_ising_L32_run.py, which calls only the oracle.
-The GPU run takes about five minutes, so the test is opt-in: set
-REWL_LONG=1.
+The GPU run takes about five minutes; REWL_SKIP_LONG=1 skips it.
 """
 import os
 
@@ -20,8 +19,8 @@ from tests.parity import gpu_context, load_golden_ising_L32_run
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.skipif(os.environ.get("REWL_LONG") != "1",
-                    reason="opt-in (REWL_LONG=1): a five-minute run to ln f = 1e-8")
+@pytest.mark.skipif(os.environ.get("REWL_SKIP_LONG") == "1",
+                    reason="REWL_SKIP_LONG=1: skips the five-minute run to ln f = 1e-8")
 def test_ising_L32_full_run_matches_stored_oracle_run():
     meta, raw, norm = load_golden_ising_L32_run()
     assert len(raw) == 1025
