@@ -260,6 +260,20 @@ int rewl_get_piece(rewl_ctx* ctx, int32_t instance, int32_t slot, double* host_l
 int rewl_jackknife(rewl_ctx* ctx, int32_t instance, double* host_mean, double* host_err,
                    int32_t capacity, int32_t* n_bins_out);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid it): rewl_jackknife with the
+ * same arguments, results and errors, whose leave-one-out rows and window
+ * representatives live in a device array of the library instead of the
+ * workspace.  It calls no allocator.  Limit: the instance's
+ * (m + 2) * nbins + (sum of its window sizes, rounded up to 32) doubles
+ * must fit in 2^19 doubles (4 MiB), else NOMEM (every Ising instance,
+ * and Potts up to L = 60, fits for any m <= 64).  Every GPU holds one such array for the life of the
+ * process and every call on that GPU uses it (it keeps the last call's
+ * contents, which no call reads), so calls that overlap on one GPU, from
+ * any context or thread, race. */
+int rewl_jackknife_noalloc(rewl_ctx* ctx, int32_t instance, double* host_mean, double* host_err,
+                           int32_t capacity, int32_t* n_bins_out);
+
 /* Synchronises.  Canonical <E> and C_V (Sec. 5, Eqs. 7-8, k_B = 1) from the joined,
  * normalised ln g of an instance, evaluated on the GPU in FP64 for nT
  * temperatures.  Errors: INVAL, HIP. */

@@ -357,6 +357,8 @@ struct rewl_ctx {
   hipGraphExec_t graph = nullptr;
   int64_t graph_flips = -1;
   int64_t graph_cycles = 0;
+  // the allocation-free jackknife's device array on this context's GPU
+  double* scratch = nullptr;
 };
 
 namespace {
@@ -548,6 +550,7 @@ int rewl_init(const rewl_params* params, int32_t n, const int32_t* win_lo, const
     e = hipMemcpyAsync(c->ws + L.o_sm, sm.data(), sizeof(int64_t) * sm.size(),
                        hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = prepare_sweep_lds((size_t)lds_budget_bytes());
+  if (e == hipSuccess) e = scratch_address(&c->scratch);
   if (e == hipSuccess) e = launch_init(c->P, c->stream);
   // host vectors above are pageable; make sure the copies finished
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -977,6 +980,30 @@ int rewl_jackknife(rewl_ctx* c, int32_t instance, double* mean, double* err, int
   rc = hip_rc(launch_jackknife(c->P, instance, c->P.rep + I.rep_base, c->P.jk, c->stream));
   if (!rc) rc = d2h(c, mean, c->P.jk + (int64_t)I.m * I.nbins, (size_t)I.nbins);
   if (!rc) rc = d2h(c, err, c->P.jk + (int64_t)(I.m + 1) * I.nbins, (size_t)I.nbins);
+  return rc;
+}
+
+int rewl_jackknife_noalloc(rewl_ctx* c, int32_t instance, double* mean, double* err,
+                           int32_t capacity, int32_t* n_bins_out) {
+  if (!c || !mean || !err || instance < 0 || instance >= (int32_t)c->lo.inst.size()) return REWL_E_INVAL;
+  const InstDesc& I = c->lo.inst[instance];
+  if (n_bins_out) *n_bins_out = I.nbins;
+  if (capacity < I.nbins) return REWL_E_INVAL;
+  if (I.m < 2) return REWL_E_STATE;
+  // representatives first, then the (m + 2) x nbins rows
+  size_t reps = 0;
+  for (int w = 0; w < I.h; ++w) reps += (size_t)c->lo.win[I.win_base + w].nb;
+  const size_t rows_at = (reps + 31) / 32 * 32;  // 256-byte aligned rows
+  if (rows_at + (size_t)(I.m + 2) * (size_t)I.nbins > kScratchDoubles) return REWL_E_NOMEM;
+  if (!c->scratch) return REWL_E_HIP;
+  InstState st;
+  int rc = d2h(c, &st, c->P.ist + instance, 1);
+  if (rc) return rc;
+  if (!st.done) return REWL_E_STATE;
+  double* jk = c->scratch + rows_at;
+  rc = hip_rc(launch_jackknife(c->P, instance, c->scratch, jk, c->stream));
+  if (!rc) rc = d2h(c, mean, jk + (int64_t)I.m * I.nbins, (size_t)I.nbins);
+  if (!rc) rc = d2h(c, err, jk + (int64_t)(I.m + 1) * I.nbins, (size_t)I.nbins);
   return rc;
 }
 

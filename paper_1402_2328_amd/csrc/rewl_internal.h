@@ -17,6 +17,11 @@ constexpr int kMaxL = 64;
 constexpr int kSweepWave = 64;    // walkers' wavefront of a sweep workgroup
 constexpr int kRngChunk = 16;     // attempts per hand-over of the RNG producer
 constexpr int kMaxTemps = 16384;  // rewl_thermo temperatures per call
+// Allocation-free jackknife: doubles of the per-GPU device array that holds
+// one instance's window representatives and (m + 2) x nbins leave-one-out
+// rows (4 MiB), and the device ordinals it serves.
+constexpr size_t kScratchDoubles = (size_t)1 << 19;
+constexpr int kMaxDevices = 64;
 
 enum Model : int32_t { kIsing = 0, kPotts = 1 };
 enum Prec : int32_t { kFP64 = 0, kFP32C = 1 };
@@ -116,6 +121,9 @@ hipError_t launch_join(const DevPtrs& P, int32_t instance, int32_t normalise, hi
 // ((m + 2) x nbins); mean and error land in rows m and m + 1.
 hipError_t launch_jackknife(const DevPtrs& P, int32_t instance, double* rep, double* jk,
                             hipStream_t s);
+// Device address, on the current GPU, of the allocation-free jackknife's
+// kScratchDoubles-double array (looked up once per device).
+hipError_t scratch_address(double** out);
 hipError_t launch_thermo(const DevPtrs& P, int32_t instance, int32_t nT, hipStream_t s);
 hipError_t prepare_sweep_lds(size_t lds_bytes);
 

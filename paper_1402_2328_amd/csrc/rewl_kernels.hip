@@ -9,6 +9,8 @@
 #include <float.h>
 #include <math.h>
 
+#include <mutex>
+
 #include "rewl_device.h"
 #include "rewl_internal.h"
 
@@ -562,6 +564,30 @@ __global__ __launch_bounds__(256) void k_jackknife(DevPtrs P, int32_t instance, 
     jk[(int64_t)m * nbins + b] = mu;
     jk[(int64_t)(m + 1) * nbins + b] = e;
   }
+}
+
+// Device memory of the allocation-free jackknife (rewl_jackknife_noalloc):
+// the window representatives and leave-one-out rows of one instance.  Every
+// GPU the library runs on holds its own copy until the process ends; calls
+// that overlap on one GPU share it.
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+hipError_t scratch_address(double** out) {
+  static std::mutex mu;
+  static double* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = static_cast<double*>(p);
+  }
+  *out = addr[dev];
+  return hipSuccess;
 }
 
 // Canonical <E> and C_V (Sec. 5, Eqs. 7-8) from the joined ln g: one thread per T.

@@ -53,7 +53,8 @@ EXPORTS = ["rewl_workspace_bytes", "rewl_init", "rewl_run_sweeps", "rewl_set_lau
            "rewl_get_lng", "rewl_get_geometry", "rewl_get_walker", "rewl_get_walker_f32",
            "rewl_get_visited", "rewl_get_exchange_stats", "rewl_thermo", "rewl_checkpoint",
            "rewl_restore", "rewl_destroy", "rewl_strerror", "rewl_get_schedule",
-           "rewl_get_piece", "rewl_jackknife", "rewl_balanced_windows", "rewl_locate_walker"]
+           "rewl_get_piece", "rewl_jackknife", "rewl_balanced_windows", "rewl_locate_walker",
+           "rewl_jackknife_noalloc"]
 
 
 def lib():
@@ -88,6 +89,7 @@ def lib():
     L.rewl_get_schedule.argtypes = [P, I32, P, P]
     L.rewl_get_piece.argtypes = [P, I32, I32, P]
     L.rewl_jackknife.argtypes = [P, I32, P, P, I32, C.POINTER(I32)]
+    L.rewl_jackknife_noalloc.argtypes = [P, I32, P, P, I32, C.POINTER(I32)]
     L.rewl_balanced_windows.argtypes = [I32, I32, I32, I32, I32, P, P, P, C.c_double, P, P]
     L.rewl_checkpoint.argtypes = [P, P, SZ, C.POINTER(SZ)]
     L.rewl_restore.argtypes = [P, P, SZ]
@@ -326,6 +328,17 @@ class Context:
         nb = C.c_int32()
         _check(lib().rewl_jackknife(self._h, instance, _p(mean), _p(err), len(mean), C.byref(nb)),
                "rewl_jackknife")
+        return mean, err
+
+    def jackknife_noalloc(self, instance=0):
+        """jackknife() through the allocation-free entry point (its scratch
+        is the library's per-GPU device array)."""
+        g = self.geometry[instance]
+        mean = np.zeros(g["nbins"], np.float64)
+        err = np.zeros(g["nbins"], np.float64)
+        nb = C.c_int32()
+        _check(lib().rewl_jackknife_noalloc(self._h, instance, _p(mean), _p(err), len(mean),
+                                            C.byref(nb)), "rewl_jackknife_noalloc")
         return mean, err
 
     def thermo(self, T, instance=0):
