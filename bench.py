@@ -12,10 +12,13 @@ from (untimed; it restores the state it touched).
 
 Printed: one JSON line with spin-flip attempts/s, the sweep kernel's
 roofline position (kernel time from HIP events recorded on the library's
-stream), the time to converge of 8 Ising L=8 instances with their error
-against the exact density of states (after the timed region), and the CPU
-oracle's attempts/s on a bounded sample, on one thread and on every host
-core (one independent instance per process).
+stream); after the timed region, the time to converge of 8 Ising L=8
+instances and of 8 Ising L=32 instances to ln f = 1e-8 in FP64 and in
+two-float FP32 (the same instances, on the balanced split), each with its
+error against the exact density of states; and the CPU oracle's
+attempts/s on a bounded sample, on one pinned core (Ising L=32, and q=10
+Potts L=20 in FP64 and FP32) and on every host core (one independent
+instance per process).  Progress lines go to stderr.
 
 --workload potts10 (q=10 Potts L=20, filled with copies) or mix (the batched
 64-instance mix) measures the other forms; --precision fp32c the two-float
@@ -85,6 +88,8 @@ def parse():
                     help="--workload mix: also time this many instances alone")
     ap.add_argument("--no-ttc", action="store_true",
                     help="skip the time-to-converge run (Ising L=8) after the throughput run")
+    ap.add_argument("--no-ttc32", action="store_true",
+                    help="skip the Ising L=32 time to ln f = 1e-8 (FP64 and FP32C, ~3 minutes)")
     ap.add_argument("--converge", action="store_true")
     ap.add_argument("--config", choices=["ising8", "ising32", "potts10", "potts10-both"],
                     default="ising32")
@@ -109,38 +114,41 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(flips, seconds):
-    from oracle import oracle as O
-    from paper_1402_2328_amd import workloads as WL
-    c = WL.ISING_L32
-    sim = O.Sim(model=c["model"], L=c["L"], n_windows=c["n_windows"],
-                walkers_per_window=c["walkers_per_window"], lnf_final=c["lnf_final"],
-                flips_per_exchange=flips, seed=c["seed"])
-    W = c["n_windows"] * c["walkers_per_window"]
-    cycles = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds:
-        sim.sweep(flips)
-        sim.merge()
-        sim.exchange()
-        cycles += 1
-    dt = time.perf_counter() - t0
-    return {"value": cycles * W * flips / dt, "unit": "attempts/s", "cores": 1, "kind": "oracle",
-            "sample": f"Ising L=32 REWL (16 windows x 8 walkers), {cycles} cycles of {flips} "
-                      f"attempts per walker from a fresh start, one thread, {dt:.1f} s",
-            "cpu": platform.processor() or platform.machine(), "host_cpus": os.cpu_count()}
+def progress(**kw):
+    """A progress line on stderr (the JSON result line alone goes to stdout)."""
+    print(json.dumps(kw), file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo where it exists)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+ORACLE_CONFIGS = {"ising32": ("ISING_L32", "Ising L=32 REWL (16 windows x 8 walkers)"),
+                  "potts10": ("POTTS_Q10_L20", "q=10 Potts L=20 REWL (32 windows x 16 walkers)"),
+                  "potts10_fp32c": ("POTTS_Q10_L20_FP32C",
+                                    "q=10 Potts L=20 REWL (32 windows x 16 walkers), two-float FP32")}
 
 
 def _oracle_worker(args):
-    """One process of the all-cores CPU baseline: instance `inst` of the Ising
-    L=32 configuration cycled for `seconds`; returns attempts made and the time taken."""
-    inst, flips, seconds = args
+    """Cycles of one oracle instance for `seconds` (pinned to `core` when
+    given); returns attempts made, the time taken and the core it ran on."""
+    name, inst, flips, seconds, core = args
+    if core is not None:
+        os.sched_setaffinity(0, {core})
     from oracle import oracle as O
     from paper_1402_2328_amd import workloads as WL
-    c = WL.ISING_L32
-    sim = O.Sim(model=c["model"], L=c["L"], n_windows=c["n_windows"],
+    c = getattr(WL, ORACLE_CONFIGS[name][0])
+    sim = O.Sim(model=c["model"], L=c["L"], q=c["q"], n_windows=c["n_windows"],
                 walkers_per_window=c["walkers_per_window"], lnf_final=c["lnf_final"],
-                flips_per_exchange=flips, seed=c["seed"], instance=inst)
+                flips_per_exchange=flips, seed=c["seed"], precision=c["precision"], instance=inst)
     W = c["n_windows"] * c["walkers_per_window"]
     cycles = 0
     t0 = time.perf_counter()
@@ -149,20 +157,43 @@ def _oracle_worker(args):
         sim.merge()
         sim.exchange()
         cycles += 1
-    return cycles * W * flips, time.perf_counter() - t0
+    return cycles * W * flips, time.perf_counter() - t0, sorted(os.sched_getaffinity(0)), cycles
+
+
+def cpu_baseline(flips, seconds):
+    """The oracle on one host core (a child process pinned to the last core
+    this process may use), on the Ising L=32 workload and, as context, on
+    q=10 Potts L=20 in FP64 and in two-float FP32."""
+    import multiprocessing as mp
+    core = sorted(os.sched_getaffinity(0))[-1]
+    rates = {}
+    with mp.get_context("spawn").Pool(1) as pool:
+        for name in ORACLE_CONFIGS:
+            sec = seconds if name == "ising32" else 2.0 * seconds / 3.0
+            att, dt, aff, cycles = pool.apply(_oracle_worker, ((name, 0, flips, sec, core),))
+            assert aff == [core]
+            rates[name] = (att / dt, dt, cycles)
+    v, dt, cycles = rates["ising32"]
+    return {"value": v, "unit": "attempts/s", "cores": 1, "kind": "oracle",
+            "sample": f"{ORACLE_CONFIGS['ising32'][1]}, {cycles} cycles of {flips} attempts per "
+                      f"walker from a fresh start, one thread pinned to core {core}, {dt:.1f} s",
+            "cpu": cpu_model(), "host_cpus": os.cpu_count(), "pinned_core": core,
+            "other_workloads": {n: {"value": r[0], "unit": "attempts/s", "seconds": r[1],
+                                    "cycles": r[2], "workload": ORACLE_CONFIGS[n][1]}
+                                for n, r in rates.items() if n != "ising32"}}
 
 
 def cpu_baseline_all_cores(flips, seconds, max_procs=16):
     """The oracle on every host core at once: independent Ising L=32 instances, one
     process each (at most max_procs, the host share of one GPU)."""
     import multiprocessing as mp
-    n = max(1, min(max_procs, os.cpu_count() or 1))
+    n = max(1, min(max_procs, len(os.sched_getaffinity(0))))
     t0 = time.perf_counter()
     with mp.get_context("spawn").Pool(n) as pool:
-        res = pool.map(_oracle_worker, [(i, flips, seconds) for i in range(n)])
+        res = pool.map(_oracle_worker, [("ising32", i, flips, seconds, None) for i in range(n)])
     wall = time.perf_counter() - t0
-    att = sum(a for a, _ in res)
-    span = max(t for _, t in res)
+    att = sum(r[0] for r in res)
+    span = max(r[1] for r in res)
     return {"value": att / span, "unit": "attempts/s", "cores": n, "kind": "oracle",
             "sample": f"{n} independent Ising L=32 REWL instances (16 windows x 8 walkers), one "
                       f"process each, {seconds:.0f} s of cycles of {flips} attempts per walker "
@@ -240,6 +271,68 @@ def time_to_converge_ising8(R=8):
             "max_abs_err_median": float(np.median(errs)) if errs else None}
 
 
+def time_to_converge_ising32(R=8, max_s=420.0):
+    """The Ising L=32 REWL configuration (16 windows x 8 walkers, halving to
+    ln f = 1e-8, F = 10^4) run to convergence by R instances in FP64 and the
+    same R instances (same seeds and instance indices, so the same initial
+    states) in two-float FP32, on the run-time balanced split (Fig. 1b)
+    planned from a first-iteration pre-run of R other seeds.  The two
+    precisions are separate contexts on separate streams, so they sweep side
+    by side (each fills only a few of the compute units).  Per precision:
+    wall time at which each instance finished, and its max |ln g error|
+    against the exact density of states."""
+    import torch
+    from paper_1402_2328_amd import rewl
+    from paper_1402_2328_amd import workloads as WL
+    base = WL.ISING_L32
+    F = base["flips_per_exchange"]
+    t_pre = time.perf_counter()
+    progress(phase="balanced-split pre-run, Ising L=32", instances=R)
+    windows, pre = balanced_split(base, R, 2.0, 60.0, quiet=True)
+    pre["wall_s_total"] = time.perf_counter() - t_pre
+    runs = {}
+    for tag, prec in (("fp64", WL.FP64), ("fp32c", WL.FP32C)):
+        stream = torch.cuda.Stream()
+        ctx = rewl.Context([WL.rewl_params_of(dict(base, precision=prec))] * R, windows=windows,
+                           stream=stream)
+        plan = ctx.autotune(F)
+        runs[tag] = {"ctx": ctx, "plan": plan, "done_at": {}}
+    exact = exact_ising_lng(base["L"])
+    fin = np.isfinite(exact)
+    t0 = time.perf_counter()
+    cycles = 0
+    while True:
+        for r in runs.values():
+            if len(r["done_at"]) < R:
+                r["ctx"].run_cycles(100, F, use_graph=True)
+        cycles += 100
+        torch.cuda.synchronize()
+        now = time.perf_counter() - t0
+        for r in runs.values():
+            for i in range(R):
+                if i not in r["done_at"] and r["ctx"].status(i)["done"]:
+                    r["done_at"][i] = now
+        if cycles % 2000 == 0:
+            progress(phase="time to converge, Ising L=32", cycles=cycles, t=round(now, 1),
+                     **{tag: len(r["done_at"]) for tag, r in runs.items()})
+        if all(len(r["done_at"]) == R for r in runs.values()) or now > max_s:
+            break
+    out = {"config": "Ising L=32, 16 windows x 8 walkers, ln f 1 -> 1e-8 by halving, F=10^4, "
+                     "balanced split (Fig. 1b)",
+           "instances": R, "balanced_prerun": pre, "cycles_polled": cycles}
+    for tag, r in runs.items():
+        ctx, done = r["ctx"], r["done_at"]
+        errs = [float(np.max(np.abs(ctx.get_lng(i)[0][fin] - exact[fin]))) for i in sorted(done)]
+        out[tag] = {"finished": len(done), "launch": r["plan"],
+                    "wall_s_median": float(np.median(list(done.values()))) if done else None,
+                    "wall_s_all": float(max(done.values())) if len(done) == R else None,
+                    "cycles_to_converge": [int(ctx.status(i)["done_merge"]) + 1 for i in sorted(done)],
+                    "max_abs_err_vs_exact": errs,
+                    "max_abs_err_median": float(np.median(errs)) if errs else None}
+        ctx.close()
+    return out
+
+
 def solo_vs_batch(cfgs, n_sample, flips, batch_cycle_s):
     """Time a cycle of n_sample instances of the batch run alone (each in a
     context of its own, autotuned like the batch) and compare the sum over
@@ -278,7 +371,7 @@ def cv_peak(ctx, i, T):
     return float(T[k] + off * h), float(y1 - 0.25 * (y0 - y2) * off)
 
 
-def balanced_split(cfg, R, alpha, max_s):
+def balanced_split(cfg, R, alpha, max_s, quiet=False):
     """Run-time balanced windows (Fig. 1b) for `cfg`: a pre-run of R
     instances with the equal split, other seeds, stopped after the first WL
     iteration (ln f_final = ln f_0 / 2), gives each window's first-iteration
@@ -291,7 +384,7 @@ def balanced_split(cfg, R, alpha, max_s):
                    schedule=WL.HALVING)
     ctx = rewl.Context([WL.rewl_params_of(pre_cfg)] * R)
     ctx.autotune(F)
-    done_at, cycles, wall = run_to_convergence(ctx, R, F, max_s, "balanced pre-run")
+    done_at, cycles, wall = run_to_convergence(ctx, R, F, max_s, "balanced pre-run", quiet=quiet)
     steps = []
     for i in sorted(done_at):
         _, sm = ctx.get_schedule(i)
@@ -577,6 +670,7 @@ def main():
         ctx.merge()
         ctx.exchange()
 
+    progress(phase="throughput", workload=name)
     for _ in range(a.warmup):
         step()
     if a.page_bins <= 0:
@@ -626,12 +720,18 @@ def main():
         # the algorithmic slot count above is that of the FP64 Ising attempt
         out["roofline"] = None
         out["kernel_ms"] = sweep_ms
+    progress(phase="throughput done", attempts_per_s=value)
     if a.workload == "ising32" and prec == WL.FP64 and not a.no_ttc:
+        progress(phase="time to converge, Ising L=8")
         out["time_to_converge"] = time_to_converge_ising8()
+        if not a.no_ttc32:
+            out["time_to_converge_ising32"] = time_to_converge_ising32()
     if a.workload == "mix" and a.solo > 0:
         out["batching"] = solo_vs_batch(cfgs, a.solo, a.flips, dt / a.steps)
     if not a.no_cpu and a.workload == "ising32":
+        progress(phase="CPU oracle baseline, one pinned core")
         out["cpu_baseline"] = cpu_baseline(a.flips, a.cpu_seconds)
+        progress(phase="CPU oracle baseline, every core")
         out["cpu_baseline_all_cores"] = cpu_baseline_all_cores(a.flips, a.cpu_seconds)
     print(json.dumps(out), flush=True)
 
