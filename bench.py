@@ -15,7 +15,8 @@ roofline position (kernel time from HIP events recorded on the library's
 stream); after the timed region, the time to converge of 8 Ising L=8
 instances and of 8 Ising L=32 instances to ln f = 1e-8 in FP64 and in
 two-float FP32 (the same instances, on the balanced split), each with its
-error against the exact density of states; and the CPU oracle's
+error against the exact density of states, the autotuned throughput of
+the batched 64-instance mix; and the CPU oracle's
 attempts/s on a bounded sample, on one pinned core (Ising L=32, and q=10
 Potts L=20 in FP64 and FP32) and on every host core (one independent
 instance per process).  Progress lines go to stderr.
@@ -331,6 +332,35 @@ def time_to_converge_ising32(R=8, max_s=420.0):
                     "max_abs_err_median": float(np.median(errs)) if errs else None}
         ctx.close()
     return out
+
+
+def mix_throughput(flips, steps=10, warmup=2, repeats=5):
+    """The 64-instance batched mix (Ising L 16-64 and q-state Potts q 2-10,
+    8-48 windows x 4-16 walkers) in one context: autotuned launch plan
+    (median of `repeats` sweeps per candidate), then `steps` timed cycles
+    (sweep, merge, exchange)."""
+    import torch
+    from paper_1402_2328_amd import rewl
+    from paper_1402_2328_amd import workloads as WL
+    cfgs = [dict(c, flips_per_exchange=flips) for c in WL.batched_mix()]
+    ctx = rewl.Context([WL.rewl_params_of(c) for c in cfgs])
+    W = sum(c["n_windows"] * c["walkers_per_window"] for c in cfgs)
+    for _ in range(warmup):
+        ctx.run_cycles(1, flips)
+    t0 = time.perf_counter()
+    plan = ctx.autotune(flips, repeats=repeats)
+    tune_s = time.perf_counter() - t0
+    ctx.run_cycles(1, flips)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.run_cycles(steps, flips)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.close()
+    return {"workload": "batched mix of 64 Ising/Potts REWL instances (L 16-64, q 2-10, 8-48 "
+                        f"windows x 4-16 walkers), F={flips}", "walkers": W, "steps": steps,
+            "attempts_per_s": W * flips * steps / dt, "ms_per_cycle": dt / steps * 1e3,
+            "launch": plan, "autotune_s": tune_s, "autotune_repeats": repeats}
 
 
 def solo_vs_batch(cfgs, n_sample, flips, batch_cycle_s):
@@ -675,7 +705,7 @@ def main():
         step()
     if a.page_bins <= 0:
         # tuned on the state the timed steps start from (tuning restores it)
-        plan = ctx.autotune(a.flips, repeats=3)
+        plan = ctx.autotune(a.flips, repeats=5 if a.workload == "mix" else 3)
     torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(a.steps)]
@@ -726,6 +756,8 @@ def main():
         out["time_to_converge"] = time_to_converge_ising8()
         if not a.no_ttc32:
             out["time_to_converge_ising32"] = time_to_converge_ising32()
+        progress(phase="batched 64-instance mix")
+        out["batched_mix"] = mix_throughput(a.flips)
     if a.workload == "mix" and a.solo > 0:
         out["batching"] = solo_vs_batch(cfgs, a.solo, a.flips, dt / a.steps)
     if not a.no_cpu and a.workload == "ising32":

@@ -141,21 +141,41 @@ int rewl_run_sweeps(rewl_ctx* ctx, int64_t flips);
  * the default (nibbles when the class has more workgroups than compute
  * units); ignored where it does not apply.  Results do not depend on the
  * shape, only speed does.  out: NULL
- * or 18 entries, per class {page_bins, walkers_per_group, LDS bytes per
- * workgroup, workgroups, rng_producer, potts_nibbles}.  Synchronises.
- * Errors: INVAL (shape does not fit in LDS), HIP. */
+ * or 21 entries: per class {page_bins, walkers_per_group, LDS bytes per
+ * workgroup, workgroups, rng_producer, potts_nibbles}, then the batch's
+ * {fused, splits, order} (rewl_set_batching).  A fused batch whose classes
+ * no longer share one rng_producer setting returns to per-class launches.
+ * Synchronises.  Errors: INVAL (shape does not fit in LDS), HIP. */
 int rewl_set_launch(rewl_ctx* ctx, int32_t cls, int32_t page_bins, int32_t walkers_per_group,
                     int32_t rng_producer, int32_t potts_nibbles, int32_t* out);
 
-/* Chooses the launch shape of every class by timing sweeps of `flips`
- * attempts (mean of `repeats` sweeps per candidate) on the whole batch:
- * classes sweep side by side and share the compute units, so a candidate
- * replaces the best plan only when the batch is faster with it.  Candidates
- * are first one page size for all classes (with and without the RNG
- * producer, Potts spins as nibbles or bytes), then, in two passes over the
- * classes, every shape of one class with the others at their best so far.
- * The plan in force before the call is the first candidate, so tuning never
- * keeps a slower plan than it started from.
+/* How a batch's sweep is launched.  fused = 0: one launch per kernel class,
+ * classes side by side on forked streams; fused = 1: every class in one
+ * launch (each workgroup runs the loop of its class, all in the LDS size
+ * of the largest class; needs one rng_producer setting for all classes).
+ * splits: a sweep of F attempts runs as that many consecutive launches
+ * (1..64; the workgroups are placed afresh for each).  order (fused only):
+ * order of the workgroups in the launch, i.e. which the hardware starts
+ * first: 0 by class (Ising L <= 32, Ising L <= 64, Potts), 1 classes
+ * reversed, 2 classes interleaved one workgroup at a time.  Results do not
+ * depend on any of these.  out: as for rewl_set_launch.  Synchronises.
+ * Errors: INVAL (out of range, or fused with differing producer
+ * settings), HIP. */
+int rewl_set_batching(rewl_ctx* ctx, int32_t fused, int32_t splits, int32_t order, int32_t* out);
+
+/* Chooses the launch shape of every class and the batching
+ * (rewl_set_batching) by timing sweeps of `flips` attempts (median of
+ * `repeats` sweeps per candidate) on the whole batch: classes sweep side by
+ * side and share the compute units, so a candidate replaces the best plan
+ * only when the batch is faster with it.  Candidates are first one page
+ * size for all classes (with and without the RNG producer, Potts spins as
+ * nibbles or bytes; for batches of several classes both per-class launches
+ * and the fused launch in each workgroup order), then, in two passes over
+ * the classes, every shape of one class with the others at their best so
+ * far, then on the best shapes the sweep in 1, 2 or 4 launches and the
+ * other batching forms.  The three best plans are then timed again, each
+ * on the mean of 4 x repeats sweeps, and the fastest on average is kept.
+ * The plan in force before the call is the first candidate.
  * The simulation state is saved to host memory first and restored
  * afterwards, so tuning changes nothing but the launch shape.  out: as for
  * rewl_set_launch.  Synchronises.

@@ -228,8 +228,15 @@ struct ClassPlan {
   int32_t nib = 0;   // Potts spins as nibbles
   size_t lds_bytes = 0;
 };
+// Batch-level choices: fused = every class in one launch (one LDS size, one
+// RNG-producer setting) rather than one launch per class on forked streams;
+// splits = launches a sweep of F attempts is cut into (same results, the
+// workgroups are placed afresh for each part); order = order of the
+// workgroup table for a fused launch (0 by class, 1 classes reversed,
+// 2 classes interleaved), i.e. which workgroups the hardware starts first.
 struct LaunchPlan {
   ClassPlan cls[3];
+  int32_t fused = 0, splits = 1, order = 0;
   std::vector<WgDesc> wg;
 };
 
@@ -305,26 +312,66 @@ int plan_class(const Layout& Lo, int cls, int lds_budget, int page_req, int g_re
 }
 
 // Builds the workgroup table: runs of up to G consecutive walkers of one
-// instance, class 0 first, then 1, then 2.
+// instance, class 0 first, then 1, then 2 (each class contiguous, as the
+// per-class launches need).  A fused plan may reorder the table: classes
+// reversed, or interleaved one workgroup of each class at a time.
 void fill_table(const Layout& Lo, LaunchPlan& pl) {
-  pl.wg.clear();
+  std::vector<WgDesc> per[3];
   for (int cls = 0; cls < 3; ++cls) {
-    ClassPlan& cp = pl.cls[cls];
-    cp.offset = (int32_t)pl.wg.size();
-    if (cp.G > 0) {
-      for (const InstDesc& I : Lo.inst) {
-        if (class_of(I) != cls) continue;
-        for (int s0 = 0; s0 < I.W; s0 += cp.G) {
-          WgDesc d{};
-          d.inst = I.inst;
-          d.slot_first = I.slot_base + s0;
-          d.count = std::min(cp.G, I.W - s0);
-          pl.wg.push_back(d);
-        }
+    const ClassPlan& cp = pl.cls[cls];
+    if (cp.G <= 0) continue;
+    for (const InstDesc& I : Lo.inst) {
+      if (class_of(I) != cls) continue;
+      for (int s0 = 0; s0 < I.W; s0 += cp.G) {
+        WgDesc d{};
+        d.inst = I.inst;
+        d.slot_first = I.slot_base + s0;
+        d.count = std::min(cp.G, I.W - s0);
+        d.cls = cls;
+        per[cls].push_back(d);
       }
     }
-    cp.count = (int32_t)pl.wg.size() - cp.offset;
   }
+  pl.wg.clear();
+  const int order = pl.fused ? pl.order : 0;
+  if (order == 2) {
+    size_t at[3] = {0, 0, 0};
+    for (bool more = true; more;) {
+      more = false;
+      for (int cls = 0; cls < 3; ++cls)
+        if (at[cls] < per[cls].size()) {
+          pl.wg.push_back(per[cls][at[cls]++]);
+          more = true;
+        }
+    }
+  } else {
+    for (int k = 0; k < 3; ++k) {
+      const int cls = order == 1 ? 2 - k : k;
+      pl.wg.insert(pl.wg.end(), per[cls].begin(), per[cls].end());
+    }
+  }
+  // per-class slices (meaningful for the per-class launches, order 0)
+  for (int cls = 0; cls < 3; ++cls) {
+    pl.cls[cls].count = (int32_t)per[cls].size();
+    pl.cls[cls].offset = 0;
+    for (size_t i = 0; i < pl.wg.size(); ++i)
+      if (pl.wg[i].cls == cls) {
+        pl.cls[cls].offset = (int32_t)i;
+        break;
+      }
+  }
+}
+
+// A fused launch needs one RNG-producer setting for every class present.
+bool fusable(const Layout& Lo, const LaunchPlan& pl) {
+  int prod = -1, classes = 0;
+  for (int cls = 0; cls < 3; ++cls) {
+    if (Lo.walkers[cls] == 0) continue;
+    ++classes;
+    if (prod >= 0 && pl.cls[cls].prod != prod) return false;
+    prod = pl.cls[cls].prod;
+  }
+  return classes > 0;
 }
 
 int plan_launch(const Layout& Lo, int lds_budget, int page_req, int g_req, LaunchPlan& pl) {
@@ -413,12 +460,39 @@ int d2h(rewl_ctx* c, T* dst, const void* src, size_t count) {
   return sync(c);
 }
 
+SweepShape shape_of(const rewl_ctx* c, int cls) {
+  const ClassPlan& cp = c->plan.cls[cls];
+  return SweepShape{cp.G, cp.nib ? c->lo.lat_words_nib[cls] : c->lo.lat_words[cls], cp.P, cp.offset, cp.nib};
+}
+
+// Attempts of part k of a sweep of `flips` cut into `parts` launches.
+int64_t part_flips(int64_t flips, int parts, int k) {
+  return flips / parts + (k < flips % parts ? 1 : 0);
+}
+
 hipError_t enqueue_sweeps(rewl_ctx* c, int64_t flips) {
+  const int parts = std::max(1, c->plan.splits);
+  hipError_t e = hipSuccess;
+  if (c->plan.fused) {
+    SweepShape sh[3];
+    size_t lds = 0;
+    for (int cls = 0; cls < 3; ++cls) {
+      sh[cls] = shape_of(c, cls);
+      lds = std::max(lds, c->plan.cls[cls].lds_bytes);
+    }
+    int prod = 0;
+    for (int cls = 0; cls < 3; ++cls)
+      if (c->plan.cls[cls].count > 0) prod = c->plan.cls[cls].prod;
+    for (int k = 0; k < parts && e == hipSuccess; ++k) {
+      const int64_t f = part_flips(flips, parts, k);
+      if (f > 0) e = launch_sweep_fused(c->P, sh, (int32_t)c->plan.wg.size(), f, lds, prod != 0, c->stream);
+    }
+    return e;
+  }
   int active[3], n = 0;
   for (int cls = 0; cls < 3; ++cls)
     if (c->plan.cls[cls].count > 0) active[n++] = cls;
   const bool fork = n > 1 && c->side[0] != nullptr;
-  hipError_t e = hipSuccess;
   if (fork) {
     e = hipEventRecord(c->fork, c->stream);
     for (int i = 1; i < n && e == hipSuccess; ++i) e = hipStreamWaitEvent(c->side[i - 1], c->fork, 0);
@@ -426,9 +500,12 @@ hipError_t enqueue_sweeps(rewl_ctx* c, int64_t flips) {
   for (int i = 0; i < n && e == hipSuccess; ++i) {
     const int cls = active[i];
     const ClassPlan& cp = c->plan.cls[cls];
-    SweepShape sh{cp.G, cp.nib ? c->lo.lat_words_nib[cls] : c->lo.lat_words[cls], cp.P, cp.offset, cp.nib};
+    const SweepShape sh = shape_of(c, cls);
     hipStream_t s = (fork && i > 0) ? c->side[i - 1] : c->stream;
-    e = launch_sweep_class(c->P, cls, sh, cp.count, flips, cp.lds_bytes, cp.prod != 0, s);
+    for (int k = 0; k < parts && e == hipSuccess; ++k) {
+      const int64_t f = part_flips(flips, parts, k);
+      if (f > 0) e = launch_sweep_class(c->P, cls, sh, cp.count, f, cp.lds_bytes, cp.prod != 0, s);
+    }
   }
   if (fork) {
     for (int i = 1; i < n && e == hipSuccess; ++i) {
@@ -601,6 +678,9 @@ void plan_out(const LaunchPlan& pl, int32_t* out) {
     out[6 * cls + 4] = pl.cls[cls].prod;
     out[6 * cls + 5] = pl.cls[cls].nib;
   }
+  out[18] = pl.fused;
+  out[19] = pl.splits;
+  out[20] = pl.order;
 }
 
 }  // namespace
@@ -619,6 +699,23 @@ int rewl_set_launch(rewl_ctx* c, int32_t cls, int32_t page_bins, int32_t walkers
                         potts_nibbles, pl.cls[k]);
     if (rc) return rc;
   }
+  // a fused launch needs one producer setting; a class change that breaks
+  // it returns the batch to per-class launches
+  if (pl.fused && !fusable(c->lo, pl)) pl.fused = 0;
+  fill_table(c->lo, pl);
+  int rc = install_plan(c, pl);
+  if (!rc) plan_out(c->plan, out);
+  return rc;
+}
+
+int rewl_set_batching(rewl_ctx* c, int32_t fused, int32_t splits, int32_t order, int32_t* out) {
+  if (!c || fused < 0 || fused > 1 || splits < 1 || splits > 64 || order < 0 || order > 2)
+    return REWL_E_INVAL;
+  LaunchPlan pl = c->plan;
+  pl.fused = fused;
+  pl.splits = splits;
+  pl.order = order;
+  if (fused && !fusable(c->lo, pl)) return REWL_E_INVAL;
   fill_table(c->lo, pl);
   int rc = install_plan(c, pl);
   if (!rc) plan_out(c->plan, out);
@@ -637,58 +734,78 @@ int rewl_autotune(rewl_ctx* c, int64_t flips, int32_t repeats, int32_t* out) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return REWL_E_HIP;
   // Every timing starts from the snapshot: the same walkers do the same
-  // attempts for every candidate.
-  // The time of a plan is the mean of `repeats` sweeps (the placement of
-  // concurrent classes on the compute units varies from sweep to sweep).
-  auto time_plan = [&](const LaunchPlan& pl, float& ms) -> int {
+  // attempts for every candidate (a sweep writes only the state between
+  // the instance table and the frozen pieces, so only that is restored).
+  // A candidate's time is the median of `repeats` sweeps: the placement of
+  // concurrent classes on the compute units varies from sweep to sweep,
+  // and a median is not pulled by one unlucky placement.
+  const size_t r_lo = L.o_ist, r_hi = L.o_pieces;
+  auto time_plan = [&](const LaunchPlan& pl, int reps, bool mean, float& ms) -> int {
     LaunchPlan q = pl;
     fill_table(L, q);
     int r = install_plan(c, q);
-    ms = 0.0f;
-    for (int k = 0; k < repeats && !r; ++k) {
-      r = hip_rc(hipMemcpyAsync(c->ws, snap.data(), c->lo.o_wg, hipMemcpyHostToDevice, c->stream));
-      if (!r) r = hip_rc(hipMemcpyAsync(c->ws + L.o_ist, snap.data() + L.o_ist, L.total - L.o_ist,
-                                         hipMemcpyHostToDevice, c->stream));
+    std::vector<float> ts;
+    for (int k = 0; k < reps && !r; ++k) {
+      r = hip_rc(hipMemcpyAsync(c->ws + r_lo, snap.data() + r_lo, r_hi - r_lo, hipMemcpyHostToDevice,
+                                c->stream));
       if (!r) r = hip_rc(hipEventRecord(e0, c->stream));
       if (!r) r = hip_rc(enqueue_sweeps(c, flips));
       if (!r) r = hip_rc(hipEventRecord(e1, c->stream));
       if (!r) r = sync(c);
       float t = 0.0f;
       if (!r) r = hip_rc(hipEventElapsedTime(&t, e0, e1));
-      ms += t / (float)repeats;
+      ts.push_back(t);
+    }
+    if (!r) {
+      std::sort(ts.begin(), ts.end());
+      const size_t n = ts.size();
+      float sum = 0.0f;
+      for (float t : ts) sum += t;
+      ms = mean ? sum / (float)n : (n % 2 ? ts[n / 2] : 0.5f * (ts[n / 2 - 1] + ts[n / 2]));
     }
     return r;
   };
   // Classes sweep side by side and share the compute units, so every
-  // candidate is timed on the whole batch, and a candidate replaces the
-  // best plan only when the whole batch is faster with it.
-  LaunchPlan best = c->plan;
-  float best_ms = 0.0f;
-  rc = time_plan(best, best_ms);
+  // candidate is timed on the whole batch.  The three best plans are kept
+  // and decided between at the end on the mean of four times the repeats,
+  // so that a plan whose time varies from sweep to sweep is judged by what
+  // it costs on average.
+  constexpr int kKeep = 3;
+  std::vector<std::pair<float, LaunchPlan>> top;
   auto consider = [&](const LaunchPlan& pl) -> int {
     float ms = 0.0f;
-    const int r = time_plan(pl, ms);
-    if (!r && ms < best_ms) {
-      best_ms = ms;
-      best = pl;
-    }
-    return r;
+    const int r = time_plan(pl, repeats, false, ms);
+    if (r) return r;
+    top.emplace_back(ms, pl);
+    std::stable_sort(top.begin(), top.end(),
+                     [](const std::pair<float, LaunchPlan>& x, const std::pair<float, LaunchPlan>& y) {
+                       return x.first < y.first;
+                     });
+    if ((int)top.size() > kKeep) top.resize(kKeep);
+    return REWL_OK;
   };
-  // Seeds: one page for every class (clamped to each class's useful
-  // range), with and without the RNG producer, Potts spins as nibbles or
-  // bytes.
-  int pmin_all = 1 << 30, pmax_all = 0;
+  auto best = [&]() -> const LaunchPlan& { return top.front().second; };
+  rc = consider(c->plan);
+  int pmin_all = 1 << 30, pmax_all = 0, classes = 0;
   for (int cls = 0; cls < 3; ++cls) {
     if (L.walkers[cls] == 0) continue;
     int pmin, pmax;
     page_range(L, cls, pmin, pmax);
     pmin_all = std::min(pmin_all, pmin);
     pmax_all = std::max(pmax_all, pmax);
+    ++classes;
   }
+  // Seeds: one page for every class (clamped to each class's useful
+  // range), with and without the RNG producer, Potts spins as nibbles or
+  // bytes; per-class launches and, with several classes, the fused launch
+  // in each workgroup order.
   for (int p = pmin_all; p <= pmax_all && !rc; p <<= 1)
     for (int prod = 0; prod < 2 && !rc; ++prod)
       for (int nib = 0; nib < (L.walkers[2] > 0 && L.nib_ok[2] ? 2 : 1) && !rc; ++nib) {
         LaunchPlan pl = c->plan;
+        pl.fused = 0;
+        pl.splits = 1;
+        pl.order = 0;
         bool ok = true;
         for (int cls = 0; cls < 3 && ok; ++cls) {
           if (L.walkers[cls] == 0) continue;
@@ -697,30 +814,71 @@ int rewl_autotune(rewl_ctx* c, int64_t flips, int32_t repeats, int32_t* out) {
           const int pc = std::min(std::max(p, pmin), pmax);
           ok = plan_class(L, cls, budget, pc, 0, prod, cls == 2 ? nib : 0, pl.cls[cls]) == 0;
         }
-        if (ok) rc = consider(pl);
+        if (!ok) continue;
+        rc = consider(pl);
+        for (int order = 0; order < 3 && classes > 1 && !rc; ++order) {
+          pl.fused = 1;
+          pl.order = order;
+          rc = consider(pl);
+        }
       }
   // Then coordinate descent, two passes over the classes: every shape of
-  // one class with the others at their best so far.
+  // one class with the others at their best so far (a fused plan stays
+  // fused while the producer settings agree).
   for (int step = 0; step < 6 && !rc; ++step) {
     const int cls = step % 3;
     if (L.walkers[cls] == 0) continue;
     int pmin, pmax;
     page_range(L, cls, pmin, pmax);
+    const LaunchPlan from = best();
     for (int p = pmin; p <= pmax && !rc; p <<= 1)
       for (int prod = 0; prod < 2 && !rc; ++prod)
         for (int nib = 0; nib < (cls == 2 && L.nib_ok[cls] ? 2 : 1) && !rc; ++nib) {
-          LaunchPlan pl = best;
+          LaunchPlan pl = from;
           if (plan_class(L, cls, budget, p, 0, prod, nib, pl.cls[cls])) continue;
+          if (pl.fused && !fusable(L, pl)) pl.fused = 0;
           rc = consider(pl);
         }
   }
+  // Batch-level choices on the best shapes: the sweep in 2 or 4 launches,
+  // and with several classes the other fused orders and per-class launches.
+  if (!rc) {
+    const LaunchPlan base = best();
+    for (int splits : {1, 2, 4}) {
+      for (int fused = 0; fused < (classes > 1 ? 2 : 1) && !rc; ++fused) {
+        for (int order = 0; order < (fused ? 3 : 1) && !rc; ++order) {
+          LaunchPlan pl = base;
+          pl.splits = splits;
+          pl.fused = fused;
+          pl.order = order;
+          if (fused && !fusable(L, pl)) continue;
+          if (pl.splits == base.splits && pl.fused == base.fused && pl.order == base.order) continue;
+          rc = consider(pl);
+        }
+      }
+    }
+  }
+  // The kept plans decided on the mean of 4 x repeats sweeps.
+  LaunchPlan chosen = c->plan;
+  if (!rc && !top.empty()) {
+    float best_mean = INFINITY;
+    const std::vector<std::pair<float, LaunchPlan>> finalists = top;
+    for (const auto& f : finalists) {
+      float ms = 0.0f;
+      rc = time_plan(f.second, 4 * repeats, true, ms);
+      if (rc) break;
+      if (ms < best_mean) {
+        best_mean = ms;
+        chosen = f.second;
+      }
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  fill_table(L, best);
-  if (!rc) rc = install_plan(c, best);
-  // restore the state (everything except the workgroup table)
-  if (!rc) rc = hip_rc(hipMemcpyAsync(c->ws, snap.data(), L.o_wg, hipMemcpyHostToDevice, c->stream));
-  if (!rc) rc = hip_rc(hipMemcpyAsync(c->ws + L.o_ist, snap.data() + L.o_ist, L.total - L.o_ist,
+  fill_table(L, chosen);
+  if (!rc) rc = install_plan(c, chosen);
+  // restore the state the sweeps touched
+  if (!rc) rc = hip_rc(hipMemcpyAsync(c->ws + r_lo, snap.data() + r_lo, r_hi - r_lo,
                                       hipMemcpyHostToDevice, c->stream));
   if (!rc) rc = sync(c);
   if (!rc) plan_out(c->plan, out);

@@ -65,8 +65,10 @@ struct InstState {
   uint64_t rounds;
 };
 
+// A sweep workgroup: up to 64 consecutive walker slots of one instance, and
+// the kernel class of that instance (0 Ising L <= 32, 1 Ising L <= 64, 2 Potts).
 struct WgDesc {
-  int32_t inst, slot_first, count, pad;
+  int32_t inst, slot_first, count, cls;
 };
 
 struct DevPtrs {
@@ -112,6 +114,10 @@ hipError_t launch_init(const DevPtrs& P, hipStream_t s);
 // 2 = Potts; n_wg workgroups starting at sh.wg_offset of the table;
 // producer: a second wavefront per workgroup computes the random numbers.
 hipError_t launch_sweep_class(const DevPtrs& P, int cls, SweepShape sh, int32_t n_wg, int64_t flips,
+                              size_t lds_bytes, bool producer, hipStream_t s);
+// Every class in one launch (k_sweep_fused): n_wg entries of the table from
+// 0, class shapes sh[0..2], lds_bytes of the largest class.
+hipError_t launch_sweep_fused(const DevPtrs& P, const SweepShape sh[3], int32_t n_wg, int64_t flips,
                               size_t lds_bytes, bool producer, hipStream_t s);
 hipError_t launch_merge(const DevPtrs& P, hipStream_t s);
 hipError_t launch_exchange(const DevPtrs& P, hipStream_t s);

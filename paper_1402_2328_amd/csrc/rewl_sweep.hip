@@ -51,11 +51,11 @@ __device__ __forceinline__ T* at_off(T* base, uint32_t byte_off) {
 // consumes the previous chunk; one workgroup barrier per chunk hands over.
 // This takes the RNG off the walkers' serial chain when few walkers share
 // the chip; the blocks are the ones the walkers would compute themselves.
+// The sweep of workgroup-table entry wgi, with the launch's dynamic LDS.
 template <int MODEL, int PREC, int ROWW, bool PROD>
-__global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(DevPtrs P, SweepShape sh,
-                                                                                int64_t flips) {
-  extern __shared__ __align__(16) unsigned char lds[];
-  const WgDesc wg = P.wg[sh.wg_offset + blockIdx.x];
+__device__ __forceinline__ void sweep_body(const DevPtrs& P, const SweepShape& sh, int64_t flips, int wgi,
+                                           unsigned char* lds) {
+  const WgDesc wg = P.wg[wgi];
   const InstDesc& Ig = P.inst[wg.inst];
   const int S = sh.stride;
   const int NWL = sh.nw;   // lattice words per lane
@@ -605,6 +605,32 @@ __global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(De
   P.att[g] = att;
 }
 
+// One kernel class per launch: the class's workgroups are entries
+// [sh.wg_offset, sh.wg_offset + gridDim.x) of the table.
+template <int MODEL, int PREC, int ROWW, bool PROD>
+__global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep(DevPtrs P, SweepShape sh,
+                                                                                int64_t flips) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  sweep_body<MODEL, PREC, ROWW, PROD>(P, sh, flips, sh.wg_offset + (int)blockIdx.x, lds);
+}
+
+// Every kernel class of a batch in one launch: workgroup b runs table entry
+// b with the loop of its class (all its lanes take the same branch), in
+// the LDS size of the largest class.  The table order decides which
+// workgroups the hardware dispatches first.
+template <int PREC, bool PROD>
+__global__ __launch_bounds__(PROD ? 2 * kSweepWave : kSweepWave) void k_sweep_fused(DevPtrs P, SweepShape s0,
+                                                                                      SweepShape s1,
+                                                                                      SweepShape s2,
+                                                                                      int64_t flips) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int wgi = (int)blockIdx.x;
+  const int cls = P.wg[wgi].cls;
+  if (cls == 0) sweep_body<kIsing, PREC, 1, PROD>(P, s0, flips, wgi, lds);
+  else if (cls == 1) sweep_body<kIsing, PREC, 2, PROD>(P, s1, flips, wgi, lds);
+  else sweep_body<kPotts, PREC, 0, PROD>(P, s2, flips, wgi, lds);
+}
+
 hipError_t prepare_sweep_lds(size_t lds_bytes) {
   const void* fns[] = {
       (const void*)k_sweep<kIsing, kFP64, 1, false>,  (const void*)k_sweep<kIsing, kFP64, 2, false>,
@@ -612,7 +638,9 @@ hipError_t prepare_sweep_lds(size_t lds_bytes) {
       (const void*)k_sweep<kIsing, kFP32C, 2, false>, (const void*)k_sweep<kPotts, kFP32C, 0, false>,
       (const void*)k_sweep<kIsing, kFP64, 1, true>,   (const void*)k_sweep<kIsing, kFP64, 2, true>,
       (const void*)k_sweep<kPotts, kFP64, 0, true>,   (const void*)k_sweep<kIsing, kFP32C, 1, true>,
-      (const void*)k_sweep<kIsing, kFP32C, 2, true>,  (const void*)k_sweep<kPotts, kFP32C, 0, true>};
+      (const void*)k_sweep<kIsing, kFP32C, 2, true>,  (const void*)k_sweep<kPotts, kFP32C, 0, true>,
+      (const void*)k_sweep_fused<kFP64, false>,       (const void*)k_sweep_fused<kFP64, true>,
+      (const void*)k_sweep_fused<kFP32C, false>,      (const void*)k_sweep_fused<kFP32C, true>};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
@@ -640,6 +668,20 @@ hipError_t launch_sweep_class(const DevPtrs& P, int cls, SweepShape sh, int32_t 
   if (n_wg <= 0) return hipSuccess;
   if (producer) launch_class<true>(P, cls, sh, dim3(n_wg), flips, lds_bytes, s);
   else launch_class<false>(P, cls, sh, dim3(n_wg), flips, lds_bytes, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_fused(const DevPtrs& P, const SweepShape sh[3], int32_t n_wg, int64_t flips,
+                              size_t lds_bytes, bool producer, hipStream_t s) {
+  if (n_wg <= 0) return hipSuccess;
+  const dim3 grid(n_wg), blk(producer ? 2 * kSweepWave : kSweepWave);
+  if (P.prec == kFP64) {
+    if (producer) hipLaunchKernelGGL((k_sweep_fused<kFP64, true>), grid, blk, lds_bytes, s, P, sh[0], sh[1], sh[2], flips);
+    else hipLaunchKernelGGL((k_sweep_fused<kFP64, false>), grid, blk, lds_bytes, s, P, sh[0], sh[1], sh[2], flips);
+  } else {
+    if (producer) hipLaunchKernelGGL((k_sweep_fused<kFP32C, true>), grid, blk, lds_bytes, s, P, sh[0], sh[1], sh[2], flips);
+    else hipLaunchKernelGGL((k_sweep_fused<kFP32C, false>), grid, blk, lds_bytes, s, P, sh[0], sh[1], sh[2], flips);
+  }
   return hipGetLastError();
 }
 

@@ -48,6 +48,7 @@ class rewl_instance_status(C.Structure):
 _lib = None
 
 EXPORTS = ["rewl_workspace_bytes", "rewl_init", "rewl_run_sweeps", "rewl_set_launch",
+           "rewl_set_batching",
            "rewl_autotune", "rewl_merge",
            "rewl_exchange", "rewl_run_cycles", "rewl_status", "rewl_running",
            "rewl_get_lng", "rewl_get_geometry", "rewl_get_walker", "rewl_get_walker_f32",
@@ -71,6 +72,7 @@ def lib():
     L.rewl_init.argtypes = [P, I32, P, P, P, SZ, P, C.POINTER(C.c_void_p)]
     L.rewl_run_sweeps.argtypes = [P, I64]
     L.rewl_set_launch.argtypes = [P, I32, I32, I32, I32, I32, P]
+    L.rewl_set_batching.argtypes = [P, I32, I32, I32, P]
     L.rewl_autotune.argtypes = [P, I64, I32, P]
     L.rewl_merge.argtypes = [P]
     L.rewl_exchange.argtypes = [P]
@@ -189,26 +191,38 @@ class Context:
 
     CLASSES = ("ising_L<=32", "ising_L<=64", "potts")
 
+    PLAN_WORDS = 21
+
     @staticmethod
     def _plan(out):
+        """Per class present: its launch shape; and, when not the default
+        (per-class launches, one launch per sweep), the batching."""
         plan = {}
         for c, name in enumerate(Context.CLASSES):
             if out[6 * c + 3] > 0:
                 plan[name] = {"page_bins": int(out[6 * c]), "walkers_per_group": int(out[6 * c + 1]),
                               "lds_bytes": int(out[6 * c + 2]), "workgroups": int(out[6 * c + 3]),
                               "rng_producer": int(out[6 * c + 4]), "potts_nibbles": int(out[6 * c + 5])}
+        if out[18] or out[19] != 1:
+            plan["batching"] = {"fused": int(out[18]), "splits": int(out[19]), "order": int(out[20])}
         return plan
 
     def set_launch(self, page_bins=0, walkers_per_group=0, cls=-1, rng_producer=-1,
                    potts_nibbles=-1):
-        out = np.zeros(18, np.int32)
+        out = np.zeros(self.PLAN_WORDS, np.int32)
         _check(lib().rewl_set_launch(self._h, int(cls), int(page_bins), int(walkers_per_group),
                                      int(rng_producer), int(potts_nibbles), _p(out)),
                "rewl_set_launch")
         return self._plan(out)
 
+    def set_batching(self, fused=0, splits=1, order=0):
+        out = np.zeros(self.PLAN_WORDS, np.int32)
+        _check(lib().rewl_set_batching(self._h, int(fused), int(splits), int(order), _p(out)),
+               "rewl_set_batching")
+        return self._plan(out)
+
     def autotune(self, flips, repeats=1):
-        out = np.zeros(18, np.int32)
+        out = np.zeros(self.PLAN_WORDS, np.int32)
         _check(lib().rewl_autotune(self._h, int(flips), int(repeats), _p(out)), "rewl_autotune")
         return self._plan(out)
 

@@ -285,6 +285,50 @@ def test_full_size_configs_sampled(cfg_name, replicas, sample, page, nib):
         compare_state(ctx, i, sim)
 
 
+BATCH = ["potts_q5_L12_h9_m7_ragged", "ising_L16_h5_m4", "ising_L40_h6_m2_tworow", "ising_L32_h4_m2"]
+
+
+@pytest.mark.parametrize("fused,splits,order,prod", [
+    (0, 3, 0, -1), (1, 1, 0, 0), (1, 2, 1, 1), (1, 1, 2, 0), (1, 4, 2, 1)])
+def test_batching_does_not_change_results(fused, splits, order, prod):
+    """Every kernel class in one batch (Ising L <= 32 with and without the
+    L = 32 rotation loop, Ising L = 40, Potts), swept per class on forked
+    streams or in one fused launch in each workgroup order, in 1 to 4
+    launches per sweep, with or without the RNG producer."""
+    cfgs = [SMALL[n] for n in BATCH]
+    ctx = gpu_context(cfgs)
+    if prod >= 0:
+        ctx.set_launch(rng_producer=prod)
+    plan = ctx.set_batching(fused=fused, splits=splits, order=order)
+    print(f"[parity] batching plan {plan}", flush=True)
+    assert plan.get("batching", {"fused": 0, "splits": 1, "order": 0}) == \
+        {"fused": fused, "splits": splits, "order": order}
+    sims = [oracle_sim(c, instance=i) for i, c in enumerate(cfgs)]
+    F = 1000
+    for seg in (3, 10):
+        ctx.run_cycles(seg, F, use_graph=seg > 5)
+        for sim in sims:
+            for _ in range(seg):
+                oracle_cycle(sim, F)
+        for i, sim in enumerate(sims):
+            compare_state(ctx, i, sim)
+
+
+def test_fused_batching_needs_one_producer_setting():
+    from paper_1402_2328_amd import rewl
+    ctx = gpu_context([SMALL[n] for n in BATCH])
+    ctx.set_launch(cls=0, rng_producer=1)
+    ctx.set_launch(cls=2, rng_producer=0)
+    with pytest.raises(rewl.RewlError) as e:
+        ctx.set_batching(fused=1)
+    assert e.value.code == -1
+    ctx.set_launch(rng_producer=0)
+    assert ctx.set_batching(fused=1)["batching"]["fused"] == 1
+    # a class change that splits the producer setting un-fuses the batch
+    plan = ctx.set_launch(cls=1, rng_producer=1)
+    assert "batching" not in plan
+
+
 def test_autotune_changes_nothing_but_speed():
     cfg = SMALL["potts_q5_L12_h9_m7_ragged"]
     ctx = gpu_context([cfg, SMALL["ising_L16_h5_m4"], SMALL["ising_L40_h6_m2_tworow"]])
@@ -312,6 +356,24 @@ def test_batched_mix_all_instances():
         print(f"[parity] batched mix instance {i}: {mix[i]['model']} L={mix[i]['L']}", flush=True)
         sim = oracle_sim(mix[i], instance=i)
         for _ in range(cycles):
+            oracle_cycle(sim, F)
+        compare_state(ctx, i, sim)
+
+
+def test_batched_mix_fused_launch_sampled():
+    """The 64-instance mix in one fused launch per part, the sweep cut into
+    two launches, workgroups of the classes interleaved; instances of every
+    class checked in full."""
+    mix = WL.batched_mix()
+    ctx = gpu_context(mix)
+    ctx.set_launch(rng_producer=0)
+    print(f"[parity] mix fused: {ctx.set_batching(fused=1, splits=2, order=2)}", flush=True)
+    F = 10000
+    ctx.run_cycles(2, F, use_graph=True)
+    for i in (0, 2, 3, 4, 6, 13, 33, 63):
+        print(f"[parity] mix fused instance {i}: {mix[i]['model']} L={mix[i]['L']}", flush=True)
+        sim = oracle_sim(mix[i], instance=i)
+        for _ in range(2):
             oracle_cycle(sim, F)
         compare_state(ctx, i, sim)
 
