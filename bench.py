@@ -446,10 +446,9 @@ def converge(a):
     sched = WL.ONE_OVER_T if a.schedule == "1t" else WL.HALVING
     out = {"metric": "time to ln f <= ln f_final", "config": name, "schedule": a.schedule,
            "instances": R, "walkers_per_window": a.walkers, "balanced": a.balanced, "runs": {}}
-    if a.schedule == "halving":
-        out["note"] = ("saved jackknife errors come from the m pieces per window, which share "
-                       "their history up to the last merge: under halving they understate the "
-                       "error; use the spread between the independent instances instead")
+    out["note"] = ("saved jackknife errors come from the m pieces per window, which share their "
+                   "history up to the last merge, so they understate the error; use the spread "
+                   "between the independent instances instead")
     saved = {}
     lng_by_run = {}
     for tag, cfg in runs:
