@@ -20,7 +20,7 @@ using namespace rewl;
 
 namespace {
 
-constexpr uint64_t kCkptMagic = 0x3230304c5745524bULL;  // "KREWL002"
+constexpr uint64_t kCkptMagic = 0x3330304c5745524bULL;  // "KREWL003"
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -120,7 +120,6 @@ int build_layout(const rewl_params* params, int32_t n, const int32_t* wlo, const
     I.lnf_final = p.lnf_final;
     I.key0 = (uint32_t)p.seed;
     I.key1 = (uint32_t)(p.seed >> 32);
-    I.invL = 1.0f / (float)p.L;
     I.schedule = p.schedule;
     I.r_base = rbase;
     I.rep_base = rep;

@@ -40,7 +40,6 @@ struct InstDesc {
   int64_t spin_base;     // byte offset of configuration 0 of this instance
   double lnf_final;
   uint32_t key0, key1;
-  float invL;
   int32_t schedule;      // kHalving or kOneOverT
 };
 

@@ -88,7 +88,6 @@ __device__ __forceinline__ void sweep_body(const DevPtrs& P, const SweepShape& s
 
   const int L = Ig.L, N = Ig.N, q = Ig.q, bshift = Ig.binw_shift;
   const bool nib = MODEL == kPotts && sh.nib != 0;
-  const float invL = Ig.invL;
   const uint32_t k0 = Ig.key0, k1 = Ig.key1;
   const uint32_t tagw = kTagMC | ((uint32_t)Ig.inst << 8);
   const int D = (MODEL == kPotts && bshift == 0) ? 4 : 2;  // largest bin step of one move
@@ -425,7 +424,10 @@ __device__ __forceinline__ void sweep_body(const DevPtrs& P, const SweepShape& s
       yd = (y + 1) & Lm;
       yu = (y - 1) & Lm;
     } else {
-      y = (int)(((float)site + 0.5f) * invL);
+      // site = floor(r.x N / 2^32) with N = L^2, so its row
+      // floor(site / L) = floor(r.x L / 2^32): one multiply, off the chain
+      // of the site itself
+      y = (int)__umulhi(r.x, (uint32_t)L);
       x = site - __mul24(y, L);
       xr = (x + 1 == L) ? 0 : x + 1;
       xl = (x == 0) ? L - 1 : x - 1;
