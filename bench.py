@@ -768,6 +768,17 @@ def main():
         out["cpu_baseline"] = cpu_baseline(a.flips, a.cpu_seconds)
         progress(phase="CPU oracle baseline, every core")
         out["cpu_baseline_all_cores"] = cpu_baseline_all_cores(a.flips, a.cpu_seconds)
+        ttc = out.get("time_to_converge_ising32", {}).get("fp64", {})
+        if ttc.get("cycles_to_converge"):
+            # the oracle's trajectory is the GPU's bit for bit, so it would need
+            # the same attempts: CPU time = attempts / the pinned oracle rate
+            W = WL.ISING_L32["n_windows"] * WL.ISING_L32["walkers_per_window"]
+            est = [c * W * a.flips / out["cpu_baseline"]["value"] for c in ttc["cycles_to_converge"]]
+            out["cpu_time_to_converge_ising32_estimate"] = {
+                "method": "attempts of each FP64 instance's GPU run to ln f = 1e-8 / single-thread "
+                          "oracle rate (cpu_baseline.value)",
+                "seconds": est, "seconds_median": float(np.median(est)),
+                "gpu_wall_s_median": ttc["wall_s_median"]}
     print(json.dumps(out), flush=True)
 
 
