@@ -137,9 +137,12 @@ int rewl_run_sweeps(rewl_ctx* ctx, int64_t flips);
  * none, -1 the default (a producer when the class has no more workgroups
  * than the GPU has compute units).  potts_nibbles (Potts class, every
  * q <= 16): 1 keeps spins in LDS as 4-bit nibbles (half the lattice, more
- * workgroups per compute unit), 0 as bytes (shorter chain per attempt), -1
- * the default (nibbles when the class has more workgroups than compute
- * units); ignored where it does not apply.  Results do not depend on the
+ * workgroups per compute unit) together with a table of every site's four
+ * neighbours (8 bytes per site, shared by the workgroup: no row, column or
+ * wrap arithmetic per attempt), 2 as nibbles without the table, 0 as bytes
+ * (shorter chain per attempt), -1 the default (form 1 when the class has
+ * more workgroups than compute units, else bytes); ignored where it does
+ * not apply.  Results do not depend on the
  * shape, only speed does.  out: NULL
  * or 21 entries: per class {page_bins, walkers_per_group, LDS bytes per
  * workgroup, workgroups, rng_producer, potts_nibbles}, then the batch's
@@ -169,12 +172,16 @@ int rewl_set_batching(rewl_ctx* ctx, int32_t fused, int32_t splits, int32_t orde
  * side and share the compute units, so a candidate replaces the best plan
  * only when the batch is faster with it.  Candidates are first one page
  * size for all classes (with and without the RNG producer, Potts spins as
- * nibbles or bytes; for batches of several classes both per-class launches
+ * bytes or nibbles, with or without the neighbour table; for batches of
+ * several classes both per-class launches
  * and the fused launch in each workgroup order), then, in two passes over
  * the classes, every shape of one class with the others at their best so
  * far, then on the best shapes the sweep in 1, 2 or 4 launches and the
- * other batching forms.  The three best plans are then timed again, each
- * on the mean of 4 x repeats sweeps, and the fastest on average is kept.
+ * other batching forms.  The three best plans are then timed as a run uses
+ * them, in runs of `repeats` consecutive sweeps from the saved state,
+ * interleaved four times, and the plan with the lowest mean plus standard
+ * deviation is kept (a plan whose time swings with the placement of
+ * concurrent kernels pays for the swings).
  * The plan in force before the call is the first candidate.
  * The simulation state is saved to host memory first and restored
  * afterwards, so tuning changes nothing but the launch shape.  out: as for

@@ -43,6 +43,7 @@ struct Layout {
   int32_t nb_max[3] = {0, 0, 0};
   int32_t potts3[3] = {0, 0, 0};
   int32_t walkers[3] = {0, 0, 0};
+  int32_t n_max[3] = {0, 0, 0};          // most sites of an instance
   int32_t prec = 0;
   // byte offsets inside the workspace
   int64_t jk_elems = 0;  // largest (m + 2) * nbins of any instance
@@ -162,6 +163,7 @@ int build_layout(const rewl_params* params, int32_t n, const int32_t* wlo, const
     Lo.nb_max[cls] = std::max(Lo.nb_max[cls], I.nbmax);
     Lo.potts3[cls] |= (I.model == REWL_POTTS && I.q >= 3);
     Lo.walkers[cls] += I.W;
+    Lo.n_max[cls] = std::max(Lo.n_max[cls], I.N);
     slot += I.W;
     win += I.h;
     spin += (int64_t)I.W * I.npad;
@@ -224,7 +226,7 @@ int build_layout(const rewl_params* params, int32_t n, const int32_t* wlo, const
 struct ClassPlan {
   int32_t G = 0, P = 0, count = 0, offset = 0;
   int32_t prod = 0;  // RNG producer wavefront per workgroup
-  int32_t nib = 0;   // Potts spins as nibbles
+  int32_t nib = 0;   // Potts spins: 0 bytes, 1 nibbles with the neighbour table, 2 nibbles
   size_t lds_bytes = 0;
 };
 // Batch-level choices: fused = every class in one launch (one LDS size, one
@@ -253,12 +255,18 @@ void page_range(const Layout& Lo, int cls, int& pmin, int& pmax) {
   pmin = std::min(Lo.potts3[cls] ? 32 : 16, pmax);
 }
 
-// LDS bytes of a workgroup of G walkers with page P; with a producer the
-// RNG double buffer (16-byte aligned) and a flag word follow the page.
-size_t lds_of(int lat, int G, int P, int prod) {
-  const size_t page_end = (size_t)G * (lat + 12 * P);
-  return prod ? align_up(page_end, 16) + (size_t)2 * kRngChunk * G * 16 + 16 : page_end;
+// LDS bytes of a workgroup of G walkers with page P: lattices and pages,
+// then (tab bytes, 8-byte aligned) the neighbour table of nibble Potts
+// lattices, then with a producer the RNG double buffer (16-byte aligned)
+// and a flag word.
+size_t lds_of(int lat, int G, int P, int prod, size_t tab) {
+  const size_t tab_end = (tab ? align_up((size_t)G * (lat + 12 * P), 8) : (size_t)G * (lat + 12 * P)) + tab;
+  return prod ? align_up(tab_end, 16) + (size_t)2 * kRngChunk * G * 16 + 16 : tab_end;
 }
+
+// Neighbour-table bytes of a class (8 per site of its largest lattice),
+// kept with nibble Potts lattices in form 1.
+size_t tab_of(const Layout& Lo, int cls, int nib) { return cls == 2 && nib == 1 ? (size_t)8 * Lo.n_max[cls] : 0; }
 
 int n_compute_units() {
   int dev = 0, v = 0;
@@ -277,8 +285,9 @@ int plan_class(const Layout& Lo, int cls, int lds_budget, int page_req, int g_re
   // has more workgroups than the GPU has compute units
   const bool many = (Lo.walkers[cls] + kSweepWave - 1) / kSweepWave > n_compute_units();
   int nib = cls == 2 && Lo.nib_ok[cls] ? (nib_req < 0 ? (many ? 1 : 0) : nib_req) : 0;
-  if (nib_req == 1 && !(cls == 2 && Lo.nib_ok[cls])) nib = 0;
+  if (nib_req >= 1 && !(cls == 2 && Lo.nib_ok[cls])) nib = 0;
   const int lat = 4 * (nib ? Lo.lat_words_nib[cls] : Lo.lat_words[cls]);
+  const size_t tab = tab_of(Lo, cls, nib);
   int pmin, pmax;
   page_range(Lo, cls, pmin, pmax);
   int P = 0, G = kSweepWave;
@@ -287,7 +296,7 @@ int plan_class(const Layout& Lo, int cls, int lds_budget, int page_req, int g_re
   } else {
     for (int T = 4; T >= 1 && P == 0; --T) {
       for (int p = pmax; p >= pmin; p >>= 1) {
-        if ((size_t)kSweepWave * T * (lat + 12 * p) <= (size_t)lds_budget) {
+        if ((size_t)T * lds_of(lat, kSweepWave, p, 0, tab) <= (size_t)lds_budget) {
           P = p;
           break;
         }
@@ -300,13 +309,13 @@ int plan_class(const Layout& Lo, int cls, int lds_budget, int page_req, int g_re
   // compute units (the walkers' chain, not issue, then bounds the sweep)
   int prod = prod_req;
   if (prod < 0) prod = (Lo.walkers[cls] + G - 1) / G <= n_compute_units() ? 1 : 0;
-  while (G > 1 && lds_of(lat, G, P, prod) > (size_t)lds_budget) --G;
-  if (lds_of(lat, G, P, prod) > (size_t)lds_budget) return REWL_E_INVAL;
+  while (G > 1 && lds_of(lat, G, P, prod, tab) > (size_t)lds_budget) --G;
+  if (lds_of(lat, G, P, prod, tab) > (size_t)lds_budget) return REWL_E_INVAL;
   cp.G = G;
   cp.P = P;
   cp.prod = prod;
   cp.nib = nib;
-  cp.lds_bytes = lds_of(lat, G, P, prod);
+  cp.lds_bytes = lds_of(lat, G, P, prod, tab);
   return REWL_OK;
 }
 
@@ -461,7 +470,8 @@ int d2h(rewl_ctx* c, T* dst, const void* src, size_t count) {
 
 SweepShape shape_of(const rewl_ctx* c, int cls) {
   const ClassPlan& cp = c->plan.cls[cls];
-  return SweepShape{cp.G, cp.nib ? c->lo.lat_words_nib[cls] : c->lo.lat_words[cls], cp.P, cp.offset, cp.nib};
+  return SweepShape{cp.G, cp.nib ? c->lo.lat_words_nib[cls] : c->lo.lat_words[cls], cp.P, cp.offset,
+                    cp.nib != 0 ? 1 : 0, cls == 2 && cp.nib == 1 ? 1 : 0};
 }
 
 // Attempts of part k of a sweep of `flips` cut into `parts` launches.
@@ -689,7 +699,7 @@ extern "C" {
 int rewl_set_launch(rewl_ctx* c, int32_t cls, int32_t page_bins, int32_t walkers_per_group,
                     int32_t rng_producer, int32_t potts_nibbles, int32_t* out) {
   if (!c || page_bins < 0 || walkers_per_group < 0 || cls < -1 || cls > 2) return REWL_E_INVAL;
-  if (rng_producer < -1 || rng_producer > 1 || potts_nibbles < -1 || potts_nibbles > 1)
+  if (rng_producer < -1 || rng_producer > 1 || potts_nibbles < -1 || potts_nibbles > 2)
     return REWL_E_INVAL;
   LaunchPlan pl = c->plan;
   for (int k = 0; k < 3; ++k) {
@@ -800,7 +810,7 @@ int rewl_autotune(rewl_ctx* c, int64_t flips, int32_t repeats, int32_t* out) {
   // in each workgroup order.
   for (int p = pmin_all; p <= pmax_all && !rc; p <<= 1)
     for (int prod = 0; prod < 2 && !rc; ++prod)
-      for (int nib = 0; nib < (L.walkers[2] > 0 && L.nib_ok[2] ? 2 : 1) && !rc; ++nib) {
+      for (int nib = 0; nib < (L.walkers[2] > 0 && L.nib_ok[2] ? 3 : 1) && !rc; ++nib) {
         LaunchPlan pl = c->plan;
         pl.fused = 0;
         pl.splits = 1;
@@ -832,7 +842,7 @@ int rewl_autotune(rewl_ctx* c, int64_t flips, int32_t repeats, int32_t* out) {
     const LaunchPlan from = best();
     for (int p = pmin; p <= pmax && !rc; p <<= 1)
       for (int prod = 0; prod < 2 && !rc; ++prod)
-        for (int nib = 0; nib < (cls == 2 && L.nib_ok[cls] ? 2 : 1) && !rc; ++nib) {
+        for (int nib = 0; nib < (cls == 2 && L.nib_ok[cls] ? 3 : 1) && !rc; ++nib) {
           LaunchPlan pl = from;
           if (plan_class(L, cls, budget, p, 0, prod, nib, pl.cls[cls])) continue;
           if (pl.fused && !fusable(L, pl)) pl.fused = 0;
@@ -857,18 +867,43 @@ int rewl_autotune(rewl_ctx* c, int64_t flips, int32_t repeats, int32_t* out) {
       }
     }
   }
-  // The kept plans decided on the mean of 4 x repeats sweeps.
+  // The kept plans decided as a run would use them: from the snapshot, runs
+  // of `repeats` consecutive sweeps (the state evolves as in a run),
+  // interleaved between the finalists four times; score = mean + standard
+  // deviation of the 4 x repeats times, so that a plan whose time swings
+  // with the placement of concurrent kernels pays for its swings.
   LaunchPlan chosen = c->plan;
   if (!rc && !top.empty()) {
-    float best_mean = INFINITY;
     const std::vector<std::pair<float, LaunchPlan>> finalists = top;
-    for (const auto& f : finalists) {
-      float ms = 0.0f;
-      rc = time_plan(f.second, 4 * repeats, true, ms);
-      if (rc) break;
-      if (ms < best_mean) {
-        best_mean = ms;
-        chosen = f.second;
+    std::vector<std::vector<float>> times(finalists.size());
+    for (int round = 0; round < 4 && !rc; ++round) {
+      for (size_t f = 0; f < finalists.size() && !rc; ++f) {
+        LaunchPlan q = finalists[f].second;
+        fill_table(L, q);
+        rc = install_plan(c, q);
+        if (!rc) rc = hip_rc(hipMemcpyAsync(c->ws + r_lo, snap.data() + r_lo, r_hi - r_lo,
+                                            hipMemcpyHostToDevice, c->stream));
+        for (int k = 0; k < repeats && !rc; ++k) {
+          rc = hip_rc(hipEventRecord(e0, c->stream));
+          if (!rc) rc = hip_rc(enqueue_sweeps(c, flips));
+          if (!rc) rc = hip_rc(hipEventRecord(e1, c->stream));
+          if (!rc) rc = sync(c);
+          float t = 0.0f;
+          if (!rc) rc = hip_rc(hipEventElapsedTime(&t, e0, e1));
+          times[f].push_back(t);
+        }
+      }
+    }
+    float best_score = INFINITY;
+    for (size_t f = 0; f < finalists.size() && !rc; ++f) {
+      double sum = 0.0, sq = 0.0;
+      for (float t : times[f]) sum += t;
+      const double mean = sum / (double)times[f].size();
+      for (float t : times[f]) sq += ((double)t - mean) * ((double)t - mean);
+      const float score = (float)(mean + sqrt(sq / (double)times[f].size()));
+      if (score < best_score) {
+        best_score = score;
+        chosen = finalists[f].second;
       }
     }
   }

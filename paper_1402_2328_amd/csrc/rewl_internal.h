@@ -101,10 +101,12 @@ struct DevPtrs {
 
 // Launch shape of one sweep kernel class (Ising L <= 32, Ising L <= 64,
 // Potts): lanes per LDS row (walkers per workgroup), 32-bit lattice words
-// per lane, ln g / H page rows per lane, first workgroup in the table, and
-// for Potts whether spins are kept as 4-bit nibbles (else bytes).
+// per lane, ln g / H page rows per lane, first workgroup in the table, for
+// Potts whether spins are kept as 4-bit nibbles (else bytes), and whether
+// the workgroup keeps a table of every site's neighbours in LDS (8 bytes
+// per site after the page; nibble lattices).
 struct SweepShape {
-  int32_t stride, nw, page, wg_offset, nib;
+  int32_t stride, nw, page, wg_offset, nib, tab;
 };
 
 // Launchers (kernels TU).  All enqueue on `s` and return the launch status.

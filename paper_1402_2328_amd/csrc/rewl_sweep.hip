@@ -63,9 +63,15 @@ __device__ __forceinline__ void sweep_body(const DevPtrs& P, const SweepShape& s
   const int PM = PG - 1;
   const int tid = threadIdx.x;
   const int lane = tid & (kSweepWave - 1);
-  // RNG double buffer [2][kRngChunk][S] after the page, at the next 16-byte
-  // boundary (its reads are 16 bytes wide), then a flag word
-  uint4* rbuf = reinterpret_cast<uint4*>(lds + (((size_t)4 * NWL * S + (size_t)12 * PG * S + 15) & ~(size_t)15));
+  // Potts nibble lattices: a table of every site's four neighbours, shared
+  // by the workgroup, 8 bytes per site after the page; then the RNG double
+  // buffer [2][kRngChunk][S] at the next 16-byte boundary (its reads are 16
+  // bytes wide), then a flag word
+  const bool use_tab = MODEL == kPotts && sh.tab != 0;
+  const size_t tab_off = ((size_t)4 * NWL * S + (size_t)12 * PG * S + 7) & ~(size_t)7;
+  uint2* tab = reinterpret_cast<uint2*>(lds + tab_off);
+  const size_t tab_end = tab_off + (use_tab ? (size_t)8 * Ig.N : 0);
+  uint4* rbuf = reinterpret_cast<uint4*>(lds + ((tab_end + 15) & ~(size_t)15));
   bool skip = P.ist[wg.inst].done || P.ist[wg.inst].error;
   if (PROD) {
     // one decision for both wavefronts: both must reach every barrier
@@ -75,6 +81,20 @@ __device__ __forceinline__ void sweep_body(const DevPtrs& P, const SweepShape& s
     skip = *flag != 0;
   }
   if (skip) return;
+  if (use_tab) {
+    // entry of site s = y L + x: for its right, left, lower and upper
+    // neighbours the lattice word (9 bits, n >> 3) and the bit offset of
+    // the nibble (5 bits, 4 (n & 7)), 14 bits each, two per 32-bit word
+    const int Lt = Ig.L;
+    for (int s = tid; s < Ig.N; s += (int)blockDim.x) {
+      const int y = s / Lt, x = s - y * Lt;
+      const int nr = y * Lt + (x + 1 == Lt ? 0 : x + 1), nl = y * Lt + (x == 0 ? Lt - 1 : x - 1);
+      const int nd = (y + 1 == Lt ? 0 : y + 1) * Lt + x, nu = (y == 0 ? Lt - 1 : y - 1) * Lt + x;
+      auto code = [](int n) { return (uint32_t)(n >> 3) | ((uint32_t)(n & 7) << 11); };
+      tab[s] = make_uint2(code(nr) | code(nl) << 14, code(nd) | code(nu) << 14);
+    }
+    __syncthreads();
+  }
   const bool active = lane < wg.count;
   const int64_t nchunks = (flips + kRngChunk - 1) / kRngChunk;
   uint32_t* lat = reinterpret_cast<uint32_t*>(lds);                           // [NWL][S]
@@ -239,9 +259,11 @@ __device__ __forceinline__ void sweep_body(const DevPtrs& P, const SweepShape& s
   // bn is the proposed bin.  bn & PM always names a slot of the page, so the
   // ln g read stays in bounds when bn lies outside the window; its value is
   // then not used.
+  uint2 tab_e = make_uint2(0u, 0u), tab_en = make_uint2(0u, 0u);  // neighbour table entries
   auto complete = [&](const uint4 r, uint4& rn, int bn, int nv, uint32_t wofs, uint32_t wrow,
-                      uint32_t fm, int site, auto nbt) -> bool {
+                      uint32_t fm, int site, auto lkt, auto nbt) -> bool {
     constexpr bool NB = decltype(nbt)::value;
+    constexpr bool TAB = decltype(lkt)::value == 3;
     const bool inwin = (bn >= lo) && (bn <= hi);
     const int jn = prow(bn & PM);
     bool acc;
@@ -257,6 +279,9 @@ __device__ __forceinline__ void sweep_body(const DevPtrs& P, const SweepShape& s
       if constexpr (!PROD) {
         rn = philox_rounds<7, 10>(rn, k0, k1);
         REWL_PIN4(rn);
+        // the next attempt's neighbour table entry, read while this
+        // attempt finishes
+        if constexpr (TAB) tab_en = tab[__umulhi(rn.x, (uint32_t)N)];
       }
       acc = inwin && a;
       lcur = acc ? ln : lcur;
@@ -273,6 +298,9 @@ __device__ __forceinline__ void sweep_body(const DevPtrs& P, const SweepShape& s
       if constexpr (!PROD) {
         rn = philox_rounds<7, 10>(rn, k0, k1);
         REWL_PIN4(rn);
+        // the next attempt's neighbour table entry, read while this
+        // attempt finishes
+        if constexpr (TAB) tab_en = tab[__umulhi(rn.x, (uint32_t)N)];
       }
       acc = inwin && a;
       hcur = acc ? nh : hcur;
@@ -412,7 +440,40 @@ __device__ __forceinline__ void sweep_body(const DevPtrs& P, const SweepShape& s
       const uint32_t vd = ~(wd ^ wrow) & fm;   // lower neighbour agrees
       const uint32_t vu = ~(wu ^ wrow) & fm;   // upper neighbour agrees
       const int bn = bin - 2 + __builtin_popcount(hz) + __builtin_popcount(vd) + __builtin_popcount(vu);
-      complete(r, rn, bn, 0, awk, wrow, fm, site, nbt);
+      complete(r, rn, bn, 0, awk, wrow, fm, site, lkt, nbt);
+      return;
+    }
+    if constexpr (LK == 3) {
+      // Potts nibbles with the neighbour table: the site's word and nibble
+      // from the site, its neighbours' from the table entry read one
+      // attempt ahead, so no row, column or wrap arithmetic
+      const uint2 e = tab_e;
+      // byte offset of lattice word wd of this lane: wd * 4S + 4 lane
+      auto word_at = [&](uint32_t wd) {
+        return *reinterpret_cast<const uint32_t*>(lds + __mul24(wd, (uint32_t)S4) + (uint32_t)lane4);
+      };
+      const uint32_t wofs = __mul24((uint32_t)site >> 3, (uint32_t)S4) + (uint32_t)lane4;
+      const uint32_t w0 = *reinterpret_cast<const uint32_t*>(lds + wofs);
+      const uint32_t w1 = word_at(__builtin_amdgcn_ubfe(e.x, 0, 9));
+      const uint32_t w2 = word_at(__builtin_amdgcn_ubfe(e.x, 14, 9));
+      const uint32_t w3 = word_at(__builtin_amdgcn_ubfe(e.y, 0, 9));
+      const uint32_t w4 = word_at(__builtin_amdgcn_ubfe(e.y, 14, 9));
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (!PROD) {
+        rn = philox_rounds<0, 4>(cn, k0, k1);
+        REWL_PIN4(rn);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      const int s0 = (int)__builtin_amdgcn_ubfe(w0, (site & 7) * 4, 4);
+      const int a = (int)__builtin_amdgcn_ubfe(w1, __builtin_amdgcn_ubfe(e.x, 9, 5), 4);
+      const int b = (int)__builtin_amdgcn_ubfe(w2, __builtin_amdgcn_ubfe(e.x, 23, 5), 4);
+      const int c = (int)__builtin_amdgcn_ubfe(w3, __builtin_amdgcn_ubfe(e.y, 9, 5), 4);
+      const int d = (int)__builtin_amdgcn_ubfe(w4, __builtin_amdgcn_ubfe(e.y, 23, 5), 4);
+      int v = s0 + 1 + (int)__umulhi(r.y, (uint32_t)(q - 1));
+      v = (v >= q) ? v - q : v;
+      const int dE = ((a == s0) + (b == s0) + (c == s0) + (d == s0)) -
+                     ((a == v) + (b == v) + (c == v) + (d == v));
+      complete(r, rn, bin + (dE >> bshift), v, wofs, w0, 0u, site, lkt, nbt);
       return;
     }
     int y, x, xr, xl, yd, yu;
@@ -511,7 +572,7 @@ __device__ __forceinline__ void sweep_body(const DevPtrs& P, const SweepShape& s
                      ((a == v) + (b == v) + (c == v) + (d == v));
       db = dE >> bshift;
     }
-    complete(r, rn, bin + db, nv, 4u * (uint32_t)widx, wrow, fm, site, nbt);
+    complete(r, rn, bin + db, nv, 4u * (uint32_t)widx, wrow, fm, site, lkt, nbt);
   };
 
 
@@ -519,12 +580,15 @@ __device__ __forceinline__ void sweep_body(const DevPtrs& P, const SweepShape& s
   using F = std::false_type;
 
   auto run = [&](auto lkt, auto nbt) {
+    constexpr bool TAB = decltype(lkt)::value == 3;
     if constexpr (!PROD) {
       uint4 r = philox10(make_uint4((uint32_t)att, (uint32_t)(att >> 32), (uint32_t)loc, tagw), k0, k1);
+      if constexpr (TAB) tab_e = tab[__umulhi(r.x, (uint32_t)N)];
       for (int64_t t = 0; t < flips; ++t) {
         uint4 rn;
         attempt(r, rn, lkt, nbt);
         r = rn;
+        if constexpr (TAB) tab_e = tab_en;
       }
     } else {
       __syncthreads();  // chunk 0 is in the buffer
@@ -532,11 +596,14 @@ __device__ __forceinline__ void sweep_body(const DevPtrs& P, const SweepShape& s
         const uint4* src = rbuf + (size_t)(c & 1) * kRngChunk * S + lane;
         const int n = (flips - c * kRngChunk) < kRngChunk ? (int)(flips - c * kRngChunk) : kRngChunk;
         uint4 r = src[0];
+        if constexpr (TAB) tab_e = tab[__umulhi(r.x, (uint32_t)N)];
         for (int i = 0; i < n; ++i) {
           const uint4 rnext = src[(size_t)(i + 1 < n ? i + 1 : i) * S];
+          if constexpr (TAB) tab_en = tab[__umulhi(rnext.x, (uint32_t)N)];
           uint4 unused;
           attempt(r, unused, lkt, nbt);
           r = rnext;
+          if constexpr (TAB) tab_e = tab_en;
         }
         __syncthreads();  // chunk c consumed, chunk c + 1 written
       }
@@ -545,7 +612,10 @@ __device__ __forceinline__ void sweep_body(const DevPtrs& P, const SweepShape& s
   using L0 = std::integral_constant<int, 0>;
   using L1 = std::integral_constant<int, 1>;
   using L2 = std::integral_constant<int, 2>;
-  if (MODEL == kPotts && nib) {
+  using L3 = std::integral_constant<int, 3>;
+  if (MODEL == kPotts && nib && use_tab) {
+    if constexpr (MODEL == kPotts) run(L3{}, T{});
+  } else if (MODEL == kPotts && nib) {
     if (pow2) run(L1{}, T{});
     else run(L0{}, T{});
   } else if (MODEL == kIsing && ROWW == 1 && L == 32) {

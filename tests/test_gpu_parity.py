@@ -227,6 +227,7 @@ def test_unreachable_window_is_reported_on_both_sides():
     ("ising_L16_h5_m4", 16, 0, 0, -1), ("ising_L16_h5_m4", 0, 5, 1, -1),
     ("ising_L16_h5_m4", 64, 0, 1, -1),
     ("potts_q5_L12_h9_m7_ragged", 32, 13, 1, 1), ("potts_q5_L12_h9_m7_ragged", 64, 0, 0, 0),
+    ("potts_q5_L12_h9_m7_ragged", 32, 0, 0, 2), ("potts_q10_L8_h4_m4", 32, 0, 1, 2),
     ("potts_q10_L8_h4_m4", 32, 3, 0, 1),
     ("potts_q20_L7_h3_m2", 32, 0, 0, 1),
     ("ising_L40_h6_m2_tworow", 16, 0, 1, -1),
@@ -238,7 +239,8 @@ def test_page_size_and_group_shape_do_not_change_results(name, page, group, prod
     """Pages much smaller than the windows make the page follow the walker
     through device memory at almost every move; with prod = 1 a second
     wavefront supplies the random numbers; nib picks the Potts lattice
-    format (nibbles need q <= 16, so q = 20 keeps bytes).  Results must not
+    format (1: nibbles with the neighbour table, 2: nibbles without, 0:
+    bytes; nibbles need q <= 16, so q = 20 keeps bytes).  Results must not
     change."""
     cfg = SMALL[name]
     ctx = gpu_context([cfg])
@@ -327,6 +329,31 @@ def test_fused_batching_needs_one_producer_setting():
     # a class change that splits the producer setting un-fuses the batch
     plan = ctx.set_launch(cls=1, rng_producer=1)
     assert "batching" not in plan
+
+
+def test_ising_L32_balanced_split_in_the_time_to_converge_launch():
+    """The benchmark's time-to-converge form of Ising L=32: 16 run-time
+    balanced windows (planned here from first-iteration step counts of the
+    shape a pre-run measures), 8 instances, each whole window in LDS, 24
+    walkers per workgroup with the RNG producer; every instance checked in
+    full after 3 cycles."""
+    from paper_1402_2328_amd import rewl
+    cfg = WL.ISING_L32
+    lo0, hi0 = O.equal_windows(1025, 16)
+    steps = [7.2e6, 2.4e6, 1.7e6, 1.2e6, 9.4e5, 6.8e5, 4.8e5, 2.7e5, 2.7e5, 4.7e5, 6.9e5, 9.2e5,
+             1.2e6, 1.7e6, 2.4e6, 7.1e6]
+    lo, hi = rewl.balanced_windows(1025, 16, lo0, hi0, steps)
+    R = 8
+    ctx = gpu_context([cfg] * R, windows=[(lo, hi)] * R)
+    plan = ctx.set_launch(page_bins=1024, walkers_per_group=24, rng_producer=1)
+    print(f"[parity] Ising L=32 balanced x{R}: windows {list(lo)}, plan {plan}", flush=True)
+    F = cfg["flips_per_exchange"]
+    ctx.run_cycles(3, F, use_graph=True)
+    for i in range(R):
+        sim = oracle_sim(cfg, instance=i, windows=(lo, hi))
+        for _ in range(3):
+            oracle_cycle(sim, F)
+        compare_state(ctx, i, sim)
 
 
 def test_autotune_changes_nothing_but_speed():
