@@ -387,6 +387,22 @@ def test_batched_mix_all_instances():
         compare_state(ctx, i, sim)
 
 
+def test_batched_mix_fp32c_autotuned_sampled():
+    """The 64-instance mix with two-float FP32 ln g, in the plan the
+    autotuner picks for it; instances of every class checked in full."""
+    mix = WL.batched_mix(precision=WL.FP32C)
+    ctx = gpu_context(mix)
+    F = 10000
+    print(f"[parity] mix fp32c: {ctx.autotune(F, repeats=2)}", flush=True)
+    ctx.run_cycles(2, F, use_graph=True)
+    for i in (1, 2, 4, 6, 33, 63):
+        print(f"[parity] mix fp32c instance {i}: {mix[i]['model']} L={mix[i]['L']}", flush=True)
+        sim = oracle_sim(mix[i], instance=i)
+        for _ in range(2):
+            oracle_cycle(sim, F)
+        compare_state(ctx, i, sim)
+
+
 def test_batched_mix_fused_launch_sampled():
     """The 64-instance mix in one fused launch per part, the sweep cut into
     two launches, workgroups of the classes interleaved; instances of every
