@@ -16,8 +16,12 @@
 //     registers and committed one attempt later, since it cannot be reached
 //     before then, so the load has a whole attempt to arrive.  Windows of
 //     at most PG bins live in LDS entirely.
-// Three compile-time copies of the attempt loop serve any L, L a power of
-// two, and Ising L = 32 (one word per row, neighbours by word rotation).
+// With nibble Potts lattices the workgroup also keeps, once for all its
+// walkers, a table of every site's four neighbours (lattice word and nibble
+// offset of each).
+// Four compile-time copies of the attempt loop serve any L, L a power of
+// two, Ising L = 32 (one word per row, neighbours by word rotation) and
+// nibble Potts lattices with the neighbour table.
 // LDS is interleaved by lane: element e of lane l sits at e * S + l (S =
 // lanes per workgroup), so the 32-bit words that one instruction touches
 // across the wavefront fall into consecutive banks.  Random numbers come
@@ -400,8 +404,9 @@ __device__ __forceinline__ void sweep_body(const DevPtrs& P, const SweepShape& s
   // the compiler from hoisting the slices back together.
   // One attempt with Philox block r; without a producer it also computes
   // rn, the block of the next attempt, in slices.  The lattice form LK
-  // (0: any L, 1: L a power of two, 2: Ising with L = 32, one word per row)
-  // and NB (Potts nibbles) select compile-time copies of the loop, chosen
+  // (0: any L, 1: L a power of two, 2: Ising with L = 32, one word per row,
+  // 3: Potts nibbles with the neighbour table) and NB (Potts nibbles)
+  // select compile-time copies of the loop, chosen
   // once per launch, so that no branch splits the attempt's scheduling
   // region.
   auto attempt = [&](const uint4 r, uint4& rn, auto lkt, auto nbt) {
