@@ -108,6 +108,8 @@ def parse():
     ap.add_argument("--save", default="", help="npz for ln g and jackknife errors (--converge)")
     ap.add_argument("--balanced", action="store_true",
                     help="--converge on the run-time balanced split planned from a pre-run")
+    ap.add_argument("--replan", action="store_true",
+                    help="--balanced: plan again from a second pre-run on the planned windows")
     ap.add_argument("--copy-reference", action="store_true",
                     help="only copy a 512 MiB device buffer 3 times (HBM counter calibration)")
     ap.add_argument("--alu-rate", action="store_true",
@@ -401,31 +403,44 @@ def cv_peak(ctx, i, T):
     return float(T[k] + off * h), float(y1 - 0.25 * (y0 - y2) * off)
 
 
-def balanced_split(cfg, R, alpha, max_s, quiet=False):
+def balanced_split(cfg, R, alpha, max_s, quiet=False, replan=False):
     """Run-time balanced windows (Fig. 1b) for `cfg`: a pre-run of R
     instances with the equal split, other seeds, stopped after the first WL
     iteration (ln f_final = ln f_0 / 2), gives each window's first-iteration
-    steps; rewl_balanced_windows turns their mean into window edges.
+    steps; rewl_balanced_windows turns their mean into window edges.  With
+    replan, a second pre-run on those windows (again other seeds) adds its
+    windows and steps, and the edges are planned again from both.
     Returns ([(lo, hi)] * R, pre-run summary)."""
     from paper_1402_2328_amd import rewl
     from paper_1402_2328_amd import workloads as WL
     F = cfg["flips_per_exchange"]
-    pre_cfg = dict(cfg, lnf_final=cfg["lnf_init"] / 2, seed=cfg["seed"] + 1000,
-                   schedule=WL.HALVING)
-    ctx = rewl.Context([WL.rewl_params_of(pre_cfg)] * R)
-    ctx.autotune(F)
-    done_at, cycles, wall = run_to_convergence(ctx, R, F, max_s, "balanced pre-run", quiet=quiet)
-    steps = []
-    for i in sorted(done_at):
-        _, sm = ctx.get_schedule(i)
-        steps.append((sm[:, 0] + 1) * F)
-    g = ctx.geometry[0]
-    mean = np.mean(np.array(steps, float), axis=0)
+
+    def pre_run(windows, seed_offset, tag):
+        pre_cfg = dict(cfg, lnf_final=cfg["lnf_init"] / 2, seed=cfg["seed"] + seed_offset,
+                       schedule=WL.HALVING)
+        ctx = rewl.Context([WL.rewl_params_of(pre_cfg)] * R, windows=windows)
+        ctx.autotune(F)
+        done_at, cycles, wall = run_to_convergence(ctx, R, F, max_s, tag, quiet=quiet)
+        steps = []
+        for i in sorted(done_at):
+            _, sm = ctx.get_schedule(i)
+            steps.append((sm[:, 0] + 1) * F)
+        g = ctx.geometry[0]
+        ctx.close()
+        return g, np.mean(np.array(steps, float), axis=0), {"instances": len(steps), "cycles": cycles,
+                                                            "wall_s": wall}
+
+    g, mean, info = pre_run(None, 1000, "balanced pre-run")
     lo, hi = rewl.balanced_windows(g["nbins"], g["h"], g["lo"], g["hi"], mean,
                                    overlap=tuple(cfg["overlap"]), alpha=alpha)
-    ctx.close()
-    pre = {"instances": len(steps), "cycles": cycles, "wall_s": wall,
-           "first_iteration_steps_mean": [float(x) for x in mean]}
+    pre = dict(info, first_iteration_steps_mean=[float(x) for x in mean])
+    if replan:
+        g2, mean2, info2 = pre_run([(lo, hi)] * R, 2000, "balanced second pre-run")
+        lo, hi = rewl.balanced_windows(g["nbins"], g["h"], np.concatenate([g["lo"], g2["lo"]]),
+                                       np.concatenate([g["hi"], g2["hi"]]),
+                                       np.concatenate([mean, mean2]),
+                                       overlap=tuple(cfg["overlap"]), alpha=alpha)
+        pre["second"] = dict(info2, first_iteration_steps_mean=[float(x) for x in mean2])
     return [(lo, hi)] * R, pre
 
 
@@ -459,7 +474,7 @@ def converge(a):
             cfg["walkers_per_window"] = a.walkers
         windows, pre = None, None
         if a.balanced:
-            windows, pre = balanced_split(cfg, R, a.alpha, a.max_minutes * 60)
+            windows, pre = balanced_split(cfg, R, a.alpha, a.max_minutes * 60, replan=a.replan)
         ctx = rewl.Context([WL.rewl_params_of(cfg)] * R, windows=windows)
         plan = ctx.autotune(cfg["flips_per_exchange"])
         done_at, cycles, wall = run_to_convergence(ctx, R, cfg["flips_per_exchange"],
