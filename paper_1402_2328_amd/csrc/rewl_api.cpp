@@ -776,15 +776,18 @@ int rewl_autotune(rewl_ctx* c, int64_t flips, int32_t repeats, int32_t* out) {
   };
   // Classes sweep side by side and share the compute units, so every
   // candidate is timed on the whole batch.  The three best plans are kept
-  // and decided between at the end on the mean of four times the repeats,
-  // so that a plan whose time varies from sweep to sweep is judged by what
-  // it costs on average.
+  // and decided between at the end (below).
+  // The best plan of each form (per-class launches, one fused launch) is
+  // kept as well and joins the finalists if the three best lack its form:
+  // a per-class plan can reach the top three on lucky placements alone.
   constexpr int kKeep = 3;
   std::vector<std::pair<float, LaunchPlan>> top;
+  std::pair<float, LaunchPlan> best_form[2] = {{INFINITY, LaunchPlan()}, {INFINITY, LaunchPlan()}};
   auto consider = [&](const LaunchPlan& pl) -> int {
     float ms = 0.0f;
     const int r = time_plan(pl, repeats, false, ms);
     if (r) return r;
+    if (ms < best_form[pl.fused ? 1 : 0].first) best_form[pl.fused ? 1 : 0] = {ms, pl};
     top.emplace_back(ms, pl);
     std::stable_sort(top.begin(), top.end(),
                      [](const std::pair<float, LaunchPlan>& x, const std::pair<float, LaunchPlan>& y) {
@@ -874,7 +877,12 @@ int rewl_autotune(rewl_ctx* c, int64_t flips, int32_t repeats, int32_t* out) {
   // with the placement of concurrent kernels pays for its swings.
   LaunchPlan chosen = c->plan;
   if (!rc && !top.empty()) {
-    const std::vector<std::pair<float, LaunchPlan>> finalists = top;
+    std::vector<std::pair<float, LaunchPlan>> finalists = top;
+    for (int form = 0; form < 2; ++form) {
+      bool present = false;
+      for (const auto& f : finalists) present = present || (f.second.fused != 0) == (form == 1);
+      if (!present && best_form[form].first < INFINITY) finalists.push_back(best_form[form]);
+    }
     std::vector<std::vector<float>> times(finalists.size());
     for (int round = 0; round < 4 && !rc; ++round) {
       for (size_t f = 0; f < finalists.size() && !rc; ++f) {
