@@ -51,6 +51,37 @@ __device__ __forceinline__ T* at_off(T* base, uint32_t byte_off) {
   return reinterpret_cast<T*>(reinterpret_cast<unsigned char*>(base) + byte_off);
 }
 
+// Potts proposal s0 -> v: the new value s0 + 1 + u (u < q - 1) taken
+// modulo q by one unsigned minimum (v - q wraps round when v < q).
+__device__ __forceinline__ int potts_wrap(int v, int q) {
+  return (int)min((uint32_t)v, (uint32_t)(v - q));
+}
+
+// Energy change / J of a Potts move s0 -> v with neighbours a, b, c, d:
+// (neighbours equal to s0) - (neighbours equal to v).  The four values are
+// packed one per BITS-bit field (BITS = 4 for q <= 16, else 8); XOR with s
+// copied into every field leaves a field zero exactly where the neighbour
+// equals s, and OR-folding each field into its top bit (shift-or by
+// BITS/2, .., 1 within the field) marks the fields that are not zero.  So
+// the change is (nonzero fields for v) - (nonzero fields for s0), without
+// compares.
+template <int BITS>
+__device__ __forceinline__ int potts_de(int a, int b, int c, int d, int s0, int v) {
+  constexpr uint32_t rep = BITS == 4 ? 0x1111u : 0x01010101u;
+  constexpr uint32_t top = BITS == 4 ? 0x8888u : 0x80808080u;
+  const uint32_t n = (uint32_t)a | ((uint32_t)b << BITS) | ((uint32_t)c << (2 * BITS)) |
+                     ((uint32_t)d << (3 * BITS));
+  auto nonzero_fields = [&](uint32_t x) {
+    if constexpr (BITS == 8) x |= x << 4;
+    x |= x << 2;
+    x |= x << 1;
+    return __builtin_popcount(x & top);
+  };
+  // rep has 25 bits for BITS = 8, beyond a 24-bit multiply
+  auto spread = [&](int x) { return BITS == 4 ? __mul24((uint32_t)x, rep) : (uint32_t)x * rep; };
+  return nonzero_fields(n ^ spread(v)) - nonzero_fields(n ^ spread(s0));
+}
+
 // PROD: the workgroup has a second wavefront that computes the Philox
 // blocks of the walkers' coming attempts, kRngChunk at a time, into a
 // double buffer in LDS (chunk c in half c mod 2) while the walker wavefront
@@ -513,10 +544,8 @@ __device__ __forceinline__ void sweep_body(const DevPtrs& P, const SweepShape& s
       const int b = (int)__builtin_amdgcn_ubfe(w2, __builtin_amdgcn_ubfe(e.x, 23, 5), 4);
       const int c = (int)__builtin_amdgcn_ubfe(w3, __builtin_amdgcn_ubfe(e.y, 9, 5), 4);
       const int d = (int)__builtin_amdgcn_ubfe(w4, __builtin_amdgcn_ubfe(e.y, 23, 5), 4);
-      int v = s0 + 1 + (int)__umulhi(r.y, (uint32_t)(q - 1));
-      v = (v >= q) ? v - q : v;
-      const int dE = ((a == s0) + (b == s0) + (c == s0) + (d == s0)) -
-                     ((a == v) + (b == v) + (c == v) + (d == v));
+      const int v = potts_wrap(s0 + 1 + (int)__umulhi(r.y, (uint32_t)(q - 1)), q);
+      const int dE = potts_de<4>(a, b, c, d, s0, v);
       complete(r, rn, bin + (dE >> bshift), v, wofs, w0, 0u, site, lkt, nbt);
       return;
     }
@@ -609,12 +638,9 @@ __device__ __forceinline__ void sweep_body(const DevPtrs& P, const SweepShape& s
         REWL_PIN4(rn);
       }
       __builtin_amdgcn_sched_barrier(0);
-      int v = s0 + 1 + (int)__umulhi(r.y, (uint32_t)(q - 1));
-      v = (v >= q) ? v - q : v;
+      const int v = potts_wrap(s0 + 1 + (int)__umulhi(r.y, (uint32_t)(q - 1)), q);
       nv = v;
-      const int dE = ((a == s0) + (b == s0) + (c == s0) + (d == s0)) -
-                     ((a == v) + (b == v) + (c == v) + (d == v));
-      db = dE >> bshift;
+      db = (NB ? potts_de<4>(a, b, c, d, s0, v) : potts_de<8>(a, b, c, d, s0, v)) >> bshift;
     }
     complete(r, rn, bin + db, nv, 4u * (uint32_t)widx, wrow, fm, site, lkt, nbt);
   };
