@@ -179,10 +179,11 @@ int rewl_set_batching(rewl_ctx* ctx, int32_t fused, int32_t splits, int32_t orde
  * far, then on the best shapes the sweep in 1, 2 or 4 launches and the
  * other batching forms.  The three best plans (with the best per-class and
  * the best fused plan when none of the three has that form) are then timed
- * as a run uses them, in runs of `repeats` consecutive sweeps from the saved state,
- * interleaved four times, and the plan with the lowest mean plus standard
- * deviation is kept (a plan whose time swings with the placement of
- * concurrent kernels pays for the swings).
+ * as a run uses them: `repeats` whole cycles (sweep, merge, exchange)
+ * queued back to back from the saved state, interleaved four times, and
+ * the plan with the lowest mean plus standard deviation of its cycle times
+ * is kept (a plan whose time swings with the placement of concurrent
+ * kernels pays for the swings).
  * The plan in force before the call is the first candidate.
  * The simulation state is saved to host memory first and restored
  * afterwards, so tuning changes nothing but the launch shape.  out: as for

@@ -870,11 +870,16 @@ int rewl_autotune(rewl_ctx* c, int64_t flips, int32_t repeats, int32_t* out) {
       }
     }
   }
-  // The kept plans decided as a run would use them: from the snapshot, runs
-  // of `repeats` consecutive sweeps (the state evolves as in a run),
+  // The kept plans decided as a run would use them: `repeats` whole cycles
+  // (sweep, merge, exchange) enqueued back to back from the saved state
+  // with no host synchronisation between them, an event between cycles;
   // interleaved between the finalists four times; score = mean + standard
-  // deviation of the 4 x repeats times, so that a plan whose time swings
-  // with the placement of concurrent kernels pays for its swings.
+  // deviation of the 4 x repeats cycle times.  Per-class launches are placed
+  // differently when the host waits after every sweep than when cycles
+  // queue up behind each other, and a plan whose time swings with the
+  // placement of concurrent kernels pays for its swings.  Merges and
+  // exchanges change more than the sweep state, so the whole workspace is
+  // restored before every run (and the plan's workgroup table rewritten).
   LaunchPlan chosen = c->plan;
   if (!rc && !top.empty()) {
     std::vector<std::pair<float, LaunchPlan>> finalists = top;
@@ -883,25 +888,31 @@ int rewl_autotune(rewl_ctx* c, int64_t flips, int32_t repeats, int32_t* out) {
       for (const auto& f : finalists) present = present || (f.second.fused != 0) == (form == 1);
       if (!present && best_form[form].first < INFINITY) finalists.push_back(best_form[form]);
     }
+    std::vector<hipEvent_t> ev((size_t)repeats + 1, nullptr);
+    for (auto& x : ev)
+      if (!rc) rc = hip_rc(hipEventCreate(&x));
     std::vector<std::vector<float>> times(finalists.size());
     for (int round = 0; round < 4 && !rc; ++round) {
       for (size_t f = 0; f < finalists.size() && !rc; ++f) {
         LaunchPlan q = finalists[f].second;
         fill_table(L, q);
-        rc = install_plan(c, q);
-        if (!rc) rc = hip_rc(hipMemcpyAsync(c->ws + r_lo, snap.data() + r_lo, r_hi - r_lo,
-                                            hipMemcpyHostToDevice, c->stream));
+        rc = hip_rc(hipMemcpyAsync(c->ws, snap.data(), L.total, hipMemcpyHostToDevice, c->stream));
+        if (!rc) rc = install_plan(c, q);
+        if (!rc) rc = hip_rc(hipEventRecord(ev[0], c->stream));
         for (int k = 0; k < repeats && !rc; ++k) {
-          rc = hip_rc(hipEventRecord(e0, c->stream));
-          if (!rc) rc = hip_rc(enqueue_sweeps(c, flips));
-          if (!rc) rc = hip_rc(hipEventRecord(e1, c->stream));
-          if (!rc) rc = sync(c);
+          rc = enqueue_cycle(c, flips);
+          if (!rc) rc = hip_rc(hipEventRecord(ev[k + 1], c->stream));
+        }
+        if (!rc) rc = sync(c);
+        for (int k = 0; k < repeats && !rc; ++k) {
           float t = 0.0f;
-          if (!rc) rc = hip_rc(hipEventElapsedTime(&t, e0, e1));
+          rc = hip_rc(hipEventElapsedTime(&t, ev[k], ev[k + 1]));
           times[f].push_back(t);
         }
       }
     }
+    for (auto& x : ev)
+      if (x) (void)hipEventDestroy(x);
     float best_score = INFINITY;
     for (size_t f = 0; f < finalists.size() && !rc; ++f) {
       double sum = 0.0, sq = 0.0;
@@ -917,11 +928,10 @@ int rewl_autotune(rewl_ctx* c, int64_t flips, int32_t repeats, int32_t* out) {
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  // restore the whole saved state, then the chosen plan's workgroup table
   fill_table(L, chosen);
+  if (!rc) rc = hip_rc(hipMemcpyAsync(c->ws, snap.data(), L.total, hipMemcpyHostToDevice, c->stream));
   if (!rc) rc = install_plan(c, chosen);
-  // restore the state the sweeps touched
-  if (!rc) rc = hip_rc(hipMemcpyAsync(c->ws + r_lo, snap.data() + r_lo, r_hi - r_lo,
-                                      hipMemcpyHostToDevice, c->stream));
   if (!rc) rc = sync(c);
   if (!rc) plan_out(c->plan, out);
   return rc;

@@ -162,12 +162,10 @@ __device__ __forceinline__ bool accept32_flat(uint32_t u, float delta) {
   return (float)u < ldexpf(p, n + 24);
 }
 
-// Median of three signed integers (v_med3_i32): clamp(a, b, c) when b <= c.
-__device__ __forceinline__ int med3_i32(int a, int b, int c) {
-  int r;
-  asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
-  return r;
-}
+// Median of three signed integers: clamp(a, b, c) when b <= c.  The
+// compiler turns this min/max form into one v_med3_i32 (and, unlike inline
+// asm, needs no wait states around it).
+__device__ __forceinline__ int med3_i32(int a, int b, int c) { return max(min(a, b), min(max(a, b), c)); }
 
 // Fast exact acceptance.  A single-precision estimate e of exp(x), x the
 // clamped delta, from the hardware base-2 exponential of x log2(e) has a

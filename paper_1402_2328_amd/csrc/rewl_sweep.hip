@@ -14,10 +14,9 @@
 //     stored, its H increments added to the histogram in device memory) and
 //     the bin that enters shares its slot; the entering ln g is loaded into
 //     registers and committed one attempt later, since it cannot be reached
-//     before then, so the load has a whole attempt to arrive (for Ising the
-//     leaving bin is read out of LDS at the shift and written back one
-//     attempt later as well).  Windows of at most PG bins live in LDS
-//     entirely.
+//     before then, so the load has a whole attempt to arrive (the leaving
+//     bin is read out of LDS at the shift and written back one attempt
+//     later as well).  Windows of at most PG bins live in LDS entirely.
 // With nibble Potts lattices the workgroup also keeps, once for all its
 // walkers, a table of every site's four neighbours (lattice word and nibble
 // offset of each).
@@ -262,13 +261,9 @@ __device__ __forceinline__ void sweep_body(const DevPtrs& P, const SweepShape& s
   }
   constexpr int DMAX = (MODEL == kPotts) ? 4 : 2;
   // Bins in flight after a page shift: for slot pend_row[i], the entering
-  // bin's ln g (loaded from device memory) and, for Ising, the leaving bin
-  // pend_e[i] with its ln g and H increments (read from LDS); both are
-  // settled one attempt later.  Deferring the write-back takes the LDS
-  // read's latency out of the shift (Ising: about 2 % faster); q >= 3
-  // Potts, with up to four bins in flight and one wave per SIMD, writes
-  // leaving bins back at once (deferring was 1 % slower there).
-  constexpr bool DEFER = MODEL == kIsing;
+  // bin's ln g (loaded from device memory) and the leaving bin pend_e[i]
+  // with its ln g and H increments (read from LDS); both are settled one
+  // attempt later, which keeps the LDS read's latency out of the shift.
   int pend_n = 0;
   int pend_row[DMAX];
   uint32_t pend_e[DMAX], ev_h[DMAX];
@@ -296,16 +291,14 @@ __device__ __forceinline__ void sweep_body(const DevPtrs& P, const SweepShape& s
           pll[j] = pend_lo[i];
         }
         pH[j] = 0;
-        if constexpr (DEFER) {
-          const uint32_t e = pend_e[i];
-          if (PREC == kFP64) {
-            *at_off(lngw, e << 3) = ev_l[i];
-          } else {
-            *at_off(lhw, e << 2) = ev_hi[i];
-            *at_off(llw, e << 2) = ev_lo[i];
-          }
-          atomicAdd(at_off(Hw, e << 2), ev_h[i]);
+        const uint32_t e = pend_e[i];
+        if (PREC == kFP64) {
+          *at_off(lngw, e << 3) = ev_l[i];
+        } else {
+          *at_off(lhw, e << 2) = ev_hi[i];
+          *at_off(llw, e << 2) = ev_lo[i];
         }
+        atomicAdd(at_off(Hw, e << 2), ev_h[i]);
       }
     }
     pend_n = 0;
@@ -433,24 +426,14 @@ __device__ __forceinline__ void sweep_body(const DevPtrs& P, const SweepShape& s
           const uint32_t e = eoff + (uint32_t)ev;
           const uint32_t en = e + (uint32_t)dpg;
           const int j = prow(ev & PM);
-          if constexpr (DEFER) {
-            if (PREC == kFP64) {
-              ev_l[i] = plg[j];
-            } else {
-              ev_hi[i] = plh[j];
-              ev_lo[i] = pll[j];
-            }
-            ev_h[i] = pH[j];
-            pend_e[i] = e;
+          if (PREC == kFP64) {
+            ev_l[i] = plg[j];
           } else {
-            if (PREC == kFP64) {
-              *at_off(lngw, e << 3) = plg[j];
-            } else {
-              *at_off(lhw, e << 2) = plh[j];
-              *at_off(llw, e << 2) = pll[j];
-            }
-            atomicAdd(at_off(Hw, e << 2), pH[j]);
+            ev_hi[i] = plh[j];
+            ev_lo[i] = pll[j];
           }
+          ev_h[i] = pH[j];
+          pend_e[i] = e;
           if (PREC == kFP64) {
             pend_l[i] = *at_off(lngw, en << 3);
           } else {
