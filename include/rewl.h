@@ -177,8 +177,8 @@ int rewl_set_batching(rewl_ctx* ctx, int32_t fused, int32_t splits, int32_t orde
  * and the fused launch in each workgroup order), then, in two passes over
  * the classes, every shape of one class with the others at their best so
  * far, then on the best shapes the sweep in 1, 2 or 4 launches and the
- * other batching forms.  The three best plans (with the best per-class and
- * the best fused plan when none of the three has that form) are then timed
+ * other batching forms.  The five best plans (with the best per-class and
+ * the best fused plan when none of the five has that form) are then timed
  * as a run uses them: `repeats` whole cycles (sweep, merge, exchange)
  * queued back to back from the saved state, interleaved four times, and
  * the plan with the lowest mean plus standard deviation of its cycle times

@@ -775,12 +775,12 @@ int rewl_autotune(rewl_ctx* c, int64_t flips, int32_t repeats, int32_t* out) {
     return r;
   };
   // Classes sweep side by side and share the compute units, so every
-  // candidate is timed on the whole batch.  The three best plans are kept
+  // candidate is timed on the whole batch.  The five best plans are kept
   // and decided between at the end (below).
   // The best plan of each form (per-class launches, one fused launch) is
-  // kept as well and joins the finalists if the three best lack its form:
-  // a per-class plan can reach the top three on lucky placements alone.
-  constexpr int kKeep = 3;
+  // kept as well and joins the finalists if the five best lack its form:
+  // a per-class plan can reach the top five on lucky placements alone.
+  constexpr int kKeep = 5;
   std::vector<std::pair<float, LaunchPlan>> top;
   std::pair<float, LaunchPlan> best_form[2] = {{INFINITY, LaunchPlan()}, {INFINITY, LaunchPlan()}};
   auto consider = [&](const LaunchPlan& pl) -> int {

@@ -162,10 +162,22 @@ __device__ __forceinline__ bool accept32_flat(uint32_t u, float delta) {
   return (float)u < ldexpf(p, n + 24);
 }
 
-// Median of three signed integers: clamp(a, b, c) when b <= c.  The
-// compiler turns this min/max form into one v_med3_i32 (and, unlike inline
-// asm, needs no wait states around it).
-__device__ __forceinline__ int med3_i32(int a, int b, int c) { return max(min(a, b), min(max(a, b), c)); }
+// Median of three signed integers: clamp(a, b, c) when b <= c, one
+// v_med3_i32 either way.  The compiler turns the min/max form into the
+// instruction and schedules it freely; written as inline asm it also gets
+// wait states around it and fixes the order of the code near it.  Which
+// of the two makes a loop faster is a matter of measurement (the sweep
+// takes ASM for Ising and the min/max form for Potts).
+template <bool ASM>
+__device__ __forceinline__ int med3_i32(int a, int b, int c) {
+  if constexpr (ASM) {
+    int r;
+    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+  } else {
+    return max(min(a, b), min(max(a, b), c));
+  }
+}
 
 // Fast exact acceptance.  A single-precision estimate e of exp(x), x the
 // clamped delta, from the hardware base-2 exponential of x log2(e) has a

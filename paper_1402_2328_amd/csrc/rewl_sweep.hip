@@ -408,7 +408,8 @@ __device__ __forceinline__ void sweep_body(const DevPtrs& P, const SweepShape& s
       // bin + M - PM is the lowest page start that still covers bin + M,
       // bin - M the highest that covers bin - M (PM >= 2M); the start then
       // stays inside [lo, hi - PM].  Both are integer medians.
-      const int nbase = med3_i32(med3_i32(base, bin + m_pm, bin - M), lo, hi_pm);
+      constexpr bool MA = MODEL == kIsing;  // Ising: 2 % faster; Potts: 1-2 % slower
+      const int nbase = med3_i32<MA>(med3_i32<MA>(base, bin + m_pm, bin - M), lo, hi_pm);
       const int sft = nbase - base;  // -D..D
       const bool up = sft > 0;
       const int shn = up ? sft : -sft;
