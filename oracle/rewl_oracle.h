@@ -33,8 +33,9 @@
  * come from this file: brute-force enumeration, exact densities of states
  * (transfer matrix, Kaufman's torus formula), closed forms, invariants and
  * planted mistakes.  One quantity has no exact reference: ln g of q >= 3
- * Potts beyond L = 4, checked only statistically (sum rule, exact
- * low-energy counts) -- parity unpinned for that quantity.
+ * Potts beyond L = 6 (exact tables exist up to q = 3, L = 6), checked only
+ * statistically (sum rule, exact low-energy counts) -- parity unpinned for
+ * that quantity.
  *
  * Error convention: functions returning int give 0 on success and a negative
  * value on error; orc_new returns NULL on invalid parameters.

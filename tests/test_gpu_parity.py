@@ -357,11 +357,21 @@ def test_ising_L32_balanced_split_in_the_time_to_converge_launch():
 
 
 def test_autotune_changes_nothing_but_speed():
+    """The tuner's final runs whole cycles (sweeps, merges, exchanges) from
+    the saved state; afterwards every counter and the trajectory are those
+    of a run that was never tuned."""
     cfg = SMALL["potts_q5_L12_h9_m7_ragged"]
     ctx = gpu_context([cfg, SMALL["ising_L16_h5_m4"], SMALL["ising_L40_h6_m2_tworow"]])
     ctx.run_cycles(4, 1500)
-    plan = ctx.autotune(1500, repeats=1)
+    keys = ("attempts", "merges", "rounds", "done", "error")
+    before = [{k: ctx.status(i)[k] for k in keys} for i in range(3)]
+    stages = [ctx.status(i)["stage"].copy() for i in range(3)]
+    plan = ctx.autotune(1500, repeats=3)
     print(f"[parity] autotune plan {plan}", flush=True)
+    for i in range(3):
+        st = ctx.status(i)
+        assert {k: st[k] for k in keys} == before[i]
+        assert np.array_equal(st["stage"], stages[i])
     ctx.run_cycles(6, 1500)
     sims = [oracle_sim(c, instance=i) for i, c in
             enumerate([cfg, SMALL["ising_L16_h5_m4"], SMALL["ising_L40_h6_m2_tworow"]])]

@@ -20,6 +20,12 @@ def load_ising_table(L):
         return np.array([int(x) for x in f if not x.startswith("#")], dtype=object)
 
 
+def load_potts_table(q, L):
+    """Counts of E = -2N + j, j = 0..2N (tests/golden/make_exact_potts.py)."""
+    with open(os.path.join(GOLD, f"potts_dos_q{q}_L{L}.txt")) as f:
+        return np.array([int(x) for x in f if not x.startswith("#")], dtype=object)
+
+
 def test_three_routes_agree_L4():
     b = X.brute_ising(4)
     t = X.transfer_ising(4)
@@ -97,3 +103,33 @@ def test_potts_low_energy_counts_q4_L4_transfer():
     for j, v in low.items():
         assert t[j] == v
     assert sum(t) == 4 ** 16
+
+
+def test_stored_potts_q3_L6_table():
+    """The q=3 L=6 table (3^36 states, beyond brute force) against what does
+    not come from the transfer matrix: the sum rule, the exact low-energy
+    counts, and the first three moments of E over all states.  With every
+    configuration equally likely, each bond's indicator delta(s_i, s_j) is
+    Bernoulli(1/q), and any three distinct bonds are independent (the
+    shortest cycle of the square lattice has four bonds), so the mean,
+    variance and third central moment of E = -sum delta are those of a sum of
+    2N independent Bernoulli(1/q) variables."""
+    q, L = 3, 6
+    N = L * L
+    c = load_potts_table(q, L)
+    assert len(c) == 2 * N + 1
+    total = sum(c)
+    assert total == q ** N
+    for j, v in X.potts_low_energy(q, L).items():
+        assert c[j] == v, j
+    E = [mp.mpf(-2 * N + j) for j in range(2 * N + 1)]
+    with mp.workdps(80):
+        m1 = mp.fsum(mp.mpf(int(v)) * e for v, e in zip(c, E)) / total
+        m2 = mp.fsum(mp.mpf(int(v)) * (e - m1) ** 2 for v, e in zip(c, E)) / total
+        m3 = mp.fsum(mp.mpf(int(v)) * (e - m1) ** 3 for v, e in zip(c, E)) / total
+        p = mp.mpf(1) / q
+        nb = 2 * N
+        assert abs(m1 - (-nb * p)) < mp.mpf("1e-60")
+        assert abs(m2 - nb * p * (1 - p)) < mp.mpf("1e-60")
+        # E = -sum delta, so its third central moment is minus that of the sum
+        assert abs(m3 - (-nb * p * (1 - p) * (1 - 2 * p))) < mp.mpf("1e-60")

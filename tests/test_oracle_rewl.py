@@ -15,7 +15,7 @@ import pytest
 
 from oracle import exact_dos as X
 from oracle import oracle as O
-from tests.test_oracle_exact import load_ising_table
+from tests.test_oracle_exact import load_ising_table, load_potts_table
 
 
 def _err_vs_exact(R, exact):
@@ -213,6 +213,33 @@ def test_rewl_potts_q3_L4_matches_brute_force():
         errs.append(_err_vs_exact(R, exact))
     # tolerance: 1.3 x the largest error over 12 seeds (0.134)
     assert max(errs) < 0.18, errs
+
+
+def test_rewl_potts_q3_L6_matches_transfer_matrix():
+    """q=3 Potts L=6 (3^36 states, beyond brute force) against the exact
+    transfer-matrix density of states: FP64 halving to ln f = 1e-6, and the
+    two-float FP32, 1/t configuration that the GPU's full-run parity test
+    uses, so that the GPU result, bitwise equal to this one, is tied to
+    exact values as well."""
+    from paper_1402_2328_amd import workloads as WL
+    from tests.parity import oracle_sim
+    exact = X.ln_g(load_potts_table(3, 6))
+    errs = []
+    for seed in (1, 2):
+        s = O.Sim(model=O.POTTS, L=6, q=3, n_windows=3, walkers_per_window=4,
+                  flips_per_exchange=300, lnf_final=1e-6, seed=seed)
+        s.run(10 ** 8)
+        assert s.status()["done"]
+        errs.append(_err_vs_exact(s.join()[0], exact))
+    # tolerance: 1.3 x the largest error over 12 seeds (0.122)
+    assert max(errs) < 0.16, errs
+    gpu_case = WL.config(WL.POTTS, 6, q=3, n_windows=3, walkers_per_window=3, lnf_final=1e-4,
+                         flips=400, seed=6, precision=WL.FP32C, schedule=WL.ONE_OVER_T)
+    s = oracle_sim(gpu_case)
+    s.run(10 ** 8)
+    assert s.status()["done"]
+    # ln f stops at 1e-4: 1.3 x the largest error over 12 seeds (0.426)
+    assert _err_vs_exact(s.join()[0], exact) < 0.55
 
 
 def test_rewl_potts_q10_sum_rule_and_ground_counts():
