@@ -47,6 +47,9 @@ SMALL = {
                                     flips=1000, seed=4, precision=WL.FP32C),
     "ising_L8_h4_m2_1t": WL.config(WL.ISING, 8, n_windows=4, walkers_per_window=2, lnf_final=1e-4,
                                    flips=500, seed=3, schedule=WL.ONE_OVER_T),
+    # its oracle run is pinned to the exact q=3 L=6 density of states
+    "potts_q3_L6_h3_m4": WL.config(WL.POTTS, 6, q=3, n_windows=3, walkers_per_window=4,
+                                   lnf_final=1e-6, flips=300, seed=1),
     "potts_q3_L6_h3_m3_1t_fp32c": WL.config(WL.POTTS, 6, q=3, n_windows=3, walkers_per_window=3,
                                             lnf_final=1e-4, flips=400, seed=6,
                                             precision=WL.FP32C, schedule=WL.ONE_OVER_T),
@@ -76,7 +79,8 @@ def test_initial_state_and_segments_match(name, prod):
 
 
 @pytest.mark.parametrize("name", ["ising_L8_h4_m2", "potts_q2_L8_h3_m2", "ising_L8_fp32c",
-                                  "ising_L8_h4_m2_1t", "potts_q3_L6_h3_m3_1t_fp32c"])
+                                  "ising_L8_h4_m2_1t", "potts_q3_L6_h3_m4",
+                                  "potts_q3_L6_h3_m3_1t_fp32c"])
 def test_full_run_to_convergence_matches(name):
     cfg = SMALL[name]
     ctx = gpu_context([cfg])

@@ -226,8 +226,9 @@ def test_rewl_potts_q3_L6_matches_transfer_matrix():
     exact = X.ln_g(load_potts_table(3, 6))
     errs = []
     for seed in (1, 2):
-        s = O.Sim(model=O.POTTS, L=6, q=3, n_windows=3, walkers_per_window=4,
-                  flips_per_exchange=300, lnf_final=1e-6, seed=seed)
+        # seed 1 is also a GPU full-run parity case
+        s = oracle_sim(WL.config(WL.POTTS, 6, q=3, n_windows=3, walkers_per_window=4,
+                                 lnf_final=1e-6, flips=300, seed=seed))
         s.run(10 ** 8)
         assert s.status()["done"]
         errs.append(_err_vs_exact(s.join()[0], exact))
