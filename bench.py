@@ -8,7 +8,7 @@ flatness 0.8, exchange every 10^4 flips, FP64 ln g) replicated R times as
 independent instances so that the chip is filled; each copy carries its
 instance index in every random-number counter.  The launch shape is chosen
 by rewl_autotune after the warm-up steps, on the state the timed steps start
-from (untimed; it restores the state it touched).
+from (untimed; it saves the whole state first and restores it).
 
 Printed: one JSON line with spin-flip attempts/s, the sweep kernel's
 roofline position (kernel time from HIP events recorded on the library's
@@ -31,7 +31,8 @@ copies of a configuration to ln f <= ln f_final and reports time to
 convergence and the C_V peak (Potts); potts10-both runs the q=10 Potts instances in
 FP64 and in two-float FP32 and compares them (progress lines precede the
 JSON line).  --balanced first plans run-time balanced windows (Fig. 1b)
-from a first-iteration pre-run.  --save keeps the normalised ln g and
+from a first-iteration pre-run (--replan: again from a second pre-run on
+those windows).  --save keeps the normalised ln g and
 jackknife errors for scoring against exact results by
 tests/converge_report.py.
 """
