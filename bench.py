@@ -221,12 +221,15 @@ def traffic_from_profile(R, flips, page):
 
 
 def run_to_convergence(ctx, R, flips, max_s, tag, quiet=False):
-    """Cycles until every instance is finished (or max_s); returns the wall
-    time at which each instance finished."""
+    """Cycles until every instance is finished or has failed (or max_s);
+    returns the wall time at which each instance finished.  A failed
+    instance (an error code in its status) stops advancing; it is reported
+    on stderr and not waited for."""
     import torch
     t0 = time.perf_counter()
     cycles = 0
     done_at = {}
+    failed = {}
     while True:
         ctx.run_cycles(100, flips, use_graph=True)
         cycles += 100
@@ -234,14 +237,17 @@ def run_to_convergence(ctx, R, flips, max_s, tag, quiet=False):
         now = time.perf_counter() - t0
         st = [ctx.status(i) for i in range(R)]
         for i, s in enumerate(st):
-            if s["done"] and i not in done_at:
+            if s["error"] and i not in failed:
+                failed[i] = int(s["error"])
+                progress(run=tag, instance=i, failed=failed[i])
+            elif s["done"] and i not in done_at:
                 done_at[i] = now
         if not quiet and (cycles % 1000 == 0 or len(done_at) == R):
             stages = np.array([s["stage"].min() for s in st])
             print(json.dumps({"run": tag, "cycles": cycles, "t": round(now, 1), "done": len(done_at),
                               "stage_min": int(stages.min()),
                               "stage_med": float(np.median(stages))}), flush=True)
-        if len(done_at) == R or now > max_s:
+        if len(done_at) + len(failed) == R or now > max_s:
             return done_at, cycles, now
 
 
@@ -302,8 +308,8 @@ def time_to_converge_ising32(R=8, max_s=420.0):
         ctx = rewl.Context([WL.rewl_params_of(dict(base, precision=prec))] * R, windows=windows,
                            stream=stream)
         plan = ctx.autotune(F)
-        runs[tag] = {"ctx": ctx, "stream": stream, "plan": plan, "done_at": {}, "cycles": 0,
-                     "over": False}
+        runs[tag] = {"ctx": ctx, "stream": stream, "plan": plan, "done_at": {}, "failed": {},
+                     "cycles": 0, "over": False}
     exact = exact_ising_lng(base["L"])
     fin = np.isfinite(exact)
     torch.cuda.synchronize()
@@ -320,9 +326,14 @@ def time_to_converge_ising32(R=8, max_s=420.0):
             now = time.perf_counter() - t0
             r["cycles"] += 100
             for i in range(R):
-                if i not in r["done_at"] and r["ctx"].status(i)["done"]:
+                if i in r["done_at"] or i in r["failed"]:
+                    continue
+                st = r["ctx"].status(i)
+                if st["error"]:
+                    r["failed"][i] = int(st["error"])   # stops advancing; reported below
+                elif st["done"]:
                     r["done_at"][i] = now
-            if len(r["done_at"]) == R or now > max_s:
+            if len(r["done_at"]) + len(r["failed"]) == R or now > max_s:
                 r["over"] = True
             else:
                 r["ctx"].run_cycles(100, F, use_graph=True)
@@ -340,7 +351,7 @@ def time_to_converge_ising32(R=8, max_s=420.0):
     for tag, r in runs.items():
         ctx, done = r["ctx"], r["done_at"]
         errs = [float(np.max(np.abs(ctx.get_lng(i)[0][fin] - exact[fin]))) for i in sorted(done)]
-        out[tag] = {"finished": len(done), "launch": r["plan"],
+        out[tag] = {"finished": len(done), "failed": r["failed"], "launch": r["plan"],
                     "wall_s_median": float(np.median(list(done.values()))) if done else None,
                     "wall_s_all": float(max(done.values())) if len(done) == R else None,
                     "cycles_to_converge": [int(ctx.status(i)["done_merge"]) + 1 for i in sorted(done)],
