@@ -307,7 +307,9 @@ def time_to_converge_ising32(R=8, max_s=420.0):
         stream = torch.cuda.Stream()
         ctx = rewl.Context([WL.rewl_params_of(dict(base, precision=prec))] * R, windows=windows,
                            stream=stream)
-        plan = ctx.autotune(F)
+        # three sweeps per candidate: with one, the choice between plans
+        # within a few per cent of each other is left to chance
+        plan = ctx.autotune(F, repeats=3)
         runs[tag] = {"ctx": ctx, "stream": stream, "plan": plan, "done_at": {}, "failed": {},
                      "cycles": 0, "over": False}
     exact = exact_ising_lng(base["L"])
@@ -501,7 +503,7 @@ def converge(a):
         if a.balanced:
             windows, pre = balanced_split(cfg, R, a.alpha, a.max_minutes * 60, replan=a.replan)
         ctx = rewl.Context([WL.rewl_params_of(cfg)] * R, windows=windows)
-        plan = ctx.autotune(cfg["flips_per_exchange"])
+        plan = ctx.autotune(cfg["flips_per_exchange"], repeats=3)
         done_at, cycles, wall = run_to_convergence(ctx, R, cfg["flips_per_exchange"],
                                                    a.max_minutes * 60 / len(runs), tag)
         g = ctx.geometry[0]
